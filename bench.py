@@ -1,0 +1,191 @@
+#!/usr/bin/env python3
+"""Benchmark of the flooding path on one MI355X.
+
+Workload (default): N = 10,000,000 float32 points on 20 noisy primitive
+surfaces in the unit cube, L = 10,000 farthest-point landmarks, k = 8
+segments per edge.  One step = landmark selection (GPU) + the flooding
+filtration (GPU: grid build, seeds, flooding search, winners) for every
+simplex of Del(L).  Del(L) is computed once on the host before the timed
+region (it is combinatorial and the landmarks are identical every step).
+
+Prints one JSON line.  `value` is executed sample-point distance
+evaluations per second over the whole step; the roofline block covers the
+flooding-search kernel, timed live with HIP events recorded by the library
+around each of its launches.
+"""
+import argparse
+import ctypes
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "flood distance evals/s + simplices/s at N=10M (% FP32 peak); batched clouds/s"
+FP32_PEAK_TFLOPS = 157.3
+FLOP_PER_EVAL = 8  # 3 sub + 1 mul + 2 fma (2 each)
+
+
+def hip_runtime():
+    for line in open("/proc/self/maps"):
+        if "libamdhip64.so" in line:
+            return ctypes.CDLL(line.split()[-1])
+    return ctypes.CDLL("libamdhip64.so")
+
+
+class HipEvents:
+    def __init__(self, n):
+        self.rt = hip_runtime()
+        self.ev = [ctypes.c_void_p() for _ in range(n)]
+        for e in self.ev:
+            assert self.rt.hipEventCreate(ctypes.byref(e)) == 0
+
+    def elapsed_ms(self, a, b):
+        ms = ctypes.c_float()
+        assert self.rt.hipEventElapsedTime(ctypes.byref(ms), self.ev[a], self.ev[b]) == 0
+        return ms.value
+
+
+def cpu_baseline(X, Lxyz, cx, k, budget_s):
+    """The oracle (masked FP64 mode) on a bounded random sample of the same
+    simplices; returns its distance evaluations per second."""
+    from oracle import flood as OF
+    from oracle import native
+    t0 = time.time()
+    xs = OF.XSorted(X)
+    prep = time.time() - t0
+    rng = np.random.default_rng(0)
+    simp = {1: cx.E, 2: cx.F, 3: cx.T}
+    tot = sum(len(simp[d]) for d in (1, 2, 3))
+    done_s, ev, ns = 0.0, np.zeros(1, np.int64), 0
+    per = 16
+    while done_s < budget_s:
+        for d in (1, 2, 3):
+            m = max(1, int(round(per * len(simp[d]) / tot)))
+            pick = rng.choice(len(simp[d]), m, replace=False)
+            t = time.time()
+            OF.flood_dim(X, Lxyz, simp[d][pick], d, k, "masked", xs, counter=ev)
+            done_s += time.time() - t
+            ns += m
+        per = min(per * 2, 4096)
+    return {"value": float(ev[0] / done_s), "unit": "evals/s", "cores": native.threads(), "kind": "oracle",
+            "sample": "masked FP64 oracle on %d random simplices of the same complex (%.1f s, %.0f simplices/s; "
+                      "x-presort %.1f s excluded)" % (ns, done_s, ns / done_s, prep)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--n-points", type=int, default=10_000_000)
+    ap.add_argument("--n-landmarks", type=int, default=10_000)
+    ap.add_argument("--k", type=int, default=8)
+    ap.add_argument("--tuning", type=str, default=None, help="JSON dict of flood_tuning fields")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: the flooding path here is single-GPU "
+              "(--gpus %d requested)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2509_22432_amd as P
+    import synth
+
+    dev = torch.device("cuda:0")
+    t0 = time.time()
+    X = synth.config_cloud(3, args.n_points)
+    gen_s = time.time() - t0
+    Xd = torch.from_numpy(X).to(dev)
+    print("bench: generated N=%d in %.1fs" % (len(X), gen_s), file=sys.stderr, flush=True)
+    idx, rad = P.fps(Xd, args.n_landmarks)
+    torch.cuda.synchronize()
+    t0 = time.time()
+    Lxyz = X[idx.cpu().numpy()]
+    cx = P.delaunay(Lxyz)
+    del_ms = (time.time() - t0) * 1e3
+    V, E, F, T = cx.counts()
+    print("bench: Del(L) %s in %.1f ms" % (cx.counts(), del_ms), file=sys.stderr, flush=True)
+    Ld = Xd[idx.long()].contiguous()
+    tuning = json.loads(args.tuning) if args.tuning else None
+    pb = P.problem_from_complexes(Xd, [0, len(X)], Ld, [0, len(Lxyz)], [cx], args.k, l_xidx=idx.clone())
+    run = P.api.FloodRun(pb, tuning, count_evals=True)
+    hev = HipEvents(8)
+    for i in range(8):
+        run.out.tile_events[i] = hev.ev[i].value
+    s0, s1, s2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+
+    def step():
+        P.fps(Xd, args.n_landmarks)
+        s1.record()
+        run.evals.zero_()
+        run()
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    fps_ms, flood_ms, tile_ms, step_ms = [], [], [], []
+    evals = []
+    t_start = torch.cuda.Event(enable_timing=True)
+    t_end = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t_start.record()
+    for _ in range(args.steps):
+        s0.record()
+        step()
+        s2.record()
+        torch.cuda.synchronize()
+        fps_ms.append(s0.elapsed_time(s1))
+        flood_ms.append(s1.elapsed_time(s2))
+        step_ms.append(s0.elapsed_time(s2))
+        tile_ms.append([hev.elapsed_ms(2 * d, 2 * d + 1) if (d == 0 or pb.n(d)) and P.n_interior(d, args.k) > 0 else 0.0
+                        for d in range(4)])
+        evals.append(int(run.evals.item()))
+    t_end.record()
+    torch.cuda.synchronize()
+    total_ms = t_start.elapsed_time(t_end)
+    ms = total_ms / args.steps
+    ev = int(np.median(evals))
+    tile_tot = float(np.mean([sum(t) for t in tile_ms]))
+    achieved = FLOP_PER_EVAL * ev / (tile_tot * 1e-3) / 1e12
+    nsimp = V + E + F + T
+    out = {
+        "metric": METRIC,
+        "value": ev / (ms * 1e-3),
+        "unit": "evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "mix20 surfaces N=%d, L=%d FPS landmarks, k=%d (plain, single cloud)"
+                               % (len(X), args.n_landmarks, args.k),
+                   "N": len(X), "L": args.n_landmarks, "k": args.k, "simplices": [V, E, F, T],
+                   "tuning": tuning},
+        "simplices_per_s": nsimp / (ms * 1e-3),
+        "evals_per_step": ev,
+        "stage_ms": {"fps": float(np.mean(fps_ms)), "filtration": float(np.mean(flood_ms)),
+                     "flood_search_per_dim": [float(np.mean([t[d] for t in tile_ms])) for d in range(4)],
+                     "delaunay_host_once": del_ms},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / FP32_PEAK_TFLOPS, "traffic": None,
+                     "kernel": "k_flood_tiles", "flop_per_eval": FLOP_PER_EVAL},
+    }
+    if not args.no_cpu_baseline:
+        print("bench: cpu baseline (oracle) ...", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(X, Lxyz, cx, args.k, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,200 @@
+/*
+ * flood.h -- C ABI of the MI355X (gfx950) flooding library.
+ *
+ * The library computes the filtration of the Flood complex (Graf et al.,
+ * "The Flood Complex", NeurIPS 2025): for every simplex sigma of the
+ * Delaunay triangulation of a landmark set L, the sampled flood value
+ *
+ *     f(sigma) = max over faces tau of sigma, max over p in P_tau of
+ *                min over x in X of ||p - x||                      (1)
+ *
+ * (Def. 1 with the sample sets of Sec. 4.1 "Approximation"), where P_tau is
+ * the barycentric grid of Lemma 6 with k segments (k+1 points) per edge:
+ * P_tau = { sum_i (a_i/k) v_i : a_i >= 0 integers, sum_i a_i = k }.
+ *
+ * Conventions for every entry point:
+ *  - Plain C types only.  "device" pointers are HIP device memory on the
+ *    current device, "host" pointers are ordinary host memory.
+ *  - Every call returns a flood_status; nothing throws or aborts.  On a
+ *    non-OK status flood_last_error() returns a thread-local message.
+ *  - All argument validation happens before any kernel is launched; a
+ *    rejected call launches nothing and writes nothing.
+ *  - Device-side calls are asynchronous on `stream` (a hipStream_t; NULL is
+ *    the default stream).  A launch failure is returned as FLOOD_EHIP; a
+ *    fault inside a kernel surfaces at the caller's next synchronisation.
+ *  - The library allocates no device memory: callers pass a workspace of at
+ *    least the size returned by the matching *_workspace_size query (any
+ *    alignment; the library aligns internally).  This keeps every device
+ *    entry point capturable in a HIP graph.  Calls that share a workspace
+ *    must not overlap.
+ *  - Coordinates are float32, row-major [n][3], contiguous.
+ */
+#ifndef FLOOD_H
+#define FLOOD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t flood_status;
+#define FLOOD_OK 0
+#define FLOOD_EINVAL 1       /* bad argument (null pointer, size, NaN/Inf input, bad offsets) */
+#define FLOOD_ENOMEM 2       /* workspace too small, or a host allocation failed */
+#define FLOOD_EHIP 3         /* a HIP runtime call or kernel launch failed */
+#define FLOOD_EDEGENERATE 4  /* degenerate geometry (see the entry point) */
+#define FLOOD_EUNSUPPORTED 5 /* outside the supported range (e.g. k > 255) */
+
+/* Message for the last non-OK status on this thread ("" if none). */
+const char *flood_last_error(void);
+
+/* ---------------------------------------------------------------------------
+ * Farthest-point landmarks (Sec. 2 "Theoretical results": greedy k-centre,
+ * a 2-approximation of the optimal covering radius; the paper's pipeline
+ * selects landmarks this way, Sec. 5 and Table 1 "Landmark select.").
+ *
+ * B clouds are processed together.  Cloud b owns points
+ * X[x_off[b] .. x_off[b+1]) and receives n_lm[b] landmarks in
+ * idx[l_off[b] .. l_off[b]+n_lm[b]), where l_off is the exclusive prefix sum
+ * of n_lm.  Indices are local to the cloud (0-based within it).
+ *
+ * Rule (bit-exact, float32): mind_i starts at +inf; for t = 0,1,..: with
+ * landmark l_t, mind_i = min(mind_i, d2(x_i, l_t)) where
+ * d2 = (dx*dx + dy*dy) + dz*dz, dx = x - l, every operation rounded to
+ * float32, no fused multiply-add; l_{t+1} = argmax_i mind_i, lowest index
+ * on ties; l_0 = start[b].  radius[l_off[b]+t] = sqrtf(max_i mind_i) after
+ * landmarks 0..t, so the last entry is d_H(X_b, L_b).
+ *
+ *   X       device float [sum N][3]
+ *   x_off   host int64 [B+1], x_off[0] = 0, non-decreasing
+ *   x_off_d device int64 [B+1], same values
+ *   n_lm    host int32 [B], 1 <= n_lm[b] <= N_b
+ *   n_lm_d  device int32 [B], same values
+ *   start_d device int64 [B] or NULL (all 0); must satisfy 0 <= start[b] < N_b
+ *   idx     device int32 [sum n_lm]              (output)
+ *   radius  device float [sum n_lm], or NULL     (output)
+ * EDEGENERATE cannot be detected before the run: if a cloud has fewer
+ * distinct points than landmarks, its remaining indices repeat an earlier
+ * landmark and its radius reaches 0; callers check radius.
+ */
+size_t flood_fps_workspace_size(int32_t B, const int64_t *x_off, const int32_t *n_lm);
+flood_status flood_fps(const float *X, int32_t B, const int64_t *x_off, const int64_t *x_off_d,
+                       const int32_t *n_lm, const int32_t *n_lm_d, const int64_t *start_d,
+                       int32_t *idx, float *radius, void *ws, size_t ws_bytes, void *stream);
+
+/* ---------------------------------------------------------------------------
+ * Delaunay triangulation of the landmarks, on the host (Sec. 4: Del(L) is
+ * the simplex set; the paper uses CGAL/qhull).  Incremental insertion with
+ * exactly evaluated orientation and in-sphere predicates (FP64 filter,
+ * exact big-integer fallback), so the result is the exact Delaunay
+ * triangulation of the given float32 coordinates.
+ *
+ *   Lxyz   host float [L][3], L >= 4, finite
+ *   out    receives a library-owned handle; free it with flood_complex_free
+ * EDEGENERATE: fewer than 4 affinely independent points, duplicate points,
+ * or an exactly coplanar/cospherical configuration that decides the
+ * triangulation (the paper assumes general position).
+ */
+typedef struct flood_complex flood_complex;
+flood_status flood_delaunay(const float *Lxyz, int32_t L, flood_complex **out);
+/* counts[0..3] = vertices, edges, triangles, tetrahedra; counts[4] = exact
+ * predicate fallbacks taken (diagnostic). */
+flood_status flood_complex_counts(const flood_complex *cx, int64_t counts[5]);
+/* Copies the complex into caller-owned host arrays sized by the counts:
+ * edges [E][2], tris [F][3], tets [T][4] -- each row sorted ascending, rows
+ * in lexicographic order; tri_edges [F][3] and tet_tris [T][4] hold the
+ * facet indices, facet i being the face without the row's i-th vertex.
+ * Any output pointer may be NULL to skip it. */
+flood_status flood_complex_export(const flood_complex *cx, int32_t *edges, int32_t *tris,
+                                  int32_t *tets, int32_t *tri_edges, int32_t *tet_tris);
+void flood_complex_free(flood_complex *cx);
+
+/* ---------------------------------------------------------------------------
+ * Flood filtration (equation (1) above), B clouds at once.
+ *
+ * Cloud b owns points X[x_off[b]..x_off[b+1]), landmarks
+ * Lxyz[l_off[b]..l_off[b+1]) and, for dimension d = 1,2,3, the simplices
+ * simp[d][s_off[d][b]..s_off[d][b+1]).  Vertex ids inside simp[] are GLOBAL
+ * landmark rows (already offset by l_off[b]); tri_edges / tet_tris hold
+ * GLOBAL edge / triangle rows.  Rows of simp[d] must be sorted ascending
+ * (the vertex order fixes the meaning of win_a).  The 0-simplices are the
+ * landmarks themselves, in order.
+ *
+ * landmarks_in_x = 1 asserts that landmark row j is the point
+ * X[l_xidx[j]] bit for bit (true for FPS landmarks); it enables the per-
+ * sample bound d(p, X) <= min_i ||p - v_i|| from the proof of Lemma 7.
+ */
+typedef struct {
+    int32_t B;               /* number of clouds, >= 1 */
+    int32_t k;               /* segments per edge, 1..255 (k+1 samples per edge) */
+    int32_t landmarks_in_x;  /* 0 or 1 (see above) */
+    int32_t reserved;
+    const float *X;          /* device [sum N][3] */
+    const int64_t *x_off;    /* host [B+1] */
+    const int64_t *x_off_d;  /* device [B+1] */
+    const float *Lxyz;       /* device [sum L][3] */
+    const int32_t *l_xidx;   /* device [sum L]: global X row of each landmark (NULL if !landmarks_in_x) */
+    const int64_t *l_off;    /* host [B+1] */
+    const int64_t *l_off_d;  /* device [B+1] */
+    const int32_t *simp[4];  /* device; simp[0] unused; simp[1] [E][2], simp[2] [F][3], simp[3] [T][4] */
+    const int64_t *s_off[4]; /* host [B+1] per dimension (s_off[0] unused) */
+    const int64_t *s_off_d[4]; /* device [B+1] per dimension (s_off_d[0] unused) */
+    const int32_t *tri_edges; /* device [F][3] */
+    const int32_t *tet_tris;  /* device [T][4] */
+} flood_problem;
+
+/* Outputs, all device.  f[d] float [n_d]: the flood value (1).  win_x[d]
+ * int32 [n_d]: global X row of the nearest point x* of the winning sample
+ * s* (lowest row among equidistant points).  win_a[d] uint32 [n_d]: the
+ * winning sample's composition a over the simplex's own vertices, a_i in
+ * bits 8i..8i+7 (s* = sum_i (a_i/k) v_i; a face-inherited winner carries
+ * zeros for the vertices it does not use; the interior sample with the
+ * lowest rank in lexicographically descending composition order wins exact
+ * ties, and the first attaining facet when the value comes from a face).
+ * evals: device uint64 [1] or NULL; receives (+=) the number of sample-point
+ * distance evaluations executed for live samples.
+ * tile_events: optional caller-created hipEvent_t handles; entries 2d and
+ * 2d+1 are recorded on `stream` right before and after the flooding-search
+ * kernel of dimension d (NULL entries are skipped).  For profiling only. */
+typedef struct {
+    float *f[4];
+    int32_t *win_x[4];
+    uint32_t *win_a[4];
+    uint64_t *evals;
+    void *tile_events[8];
+} flood_outputs;
+
+/* Tuning knobs; pass NULL for the defaults.  They change speed, never the
+ * values: cells_per_point (target uniform-grid cells per point, 0.05..64),
+ * samples_per_lane (1..4), waves_per_block (1..16). */
+typedef struct {
+    float cells_per_point;
+    int32_t samples_per_lane;
+    int32_t waves_per_block;
+    int32_t reserved;
+} flood_tuning;
+
+size_t flood_filtration_workspace_size(const flood_problem *pb, const flood_tuning *tune);
+flood_status flood_filtration(const flood_problem *pb, const flood_tuning *tune,
+                              const flood_outputs *out, void *ws, size_t ws_bytes, void *stream);
+
+/* ---------------------------------------------------------------------------
+ * Backward of loss(f) through (1), using the winners of a forward call.
+ * Away from ties, f(sigma) = ||s* - x*|| with s* = sum_i (a_i/k) v_i, so
+ * with u = (s* - x*)/||s* - x*|| (u = 0 when f = 0):
+ *     grad_X[x*]  -= g u,      grad_L[v_i] += g (a_i / k) u,
+ * g = grad_f[d][sigma].  grad_X [sum N][3] and grad_L [sum L][3] (device)
+ * are accumulated into (+=); the caller zeroes them.  Uses float atomics,
+ * so the summation order (not the terms) varies between runs.
+ *   grad_f[d] device float [n_d] or NULL (treated as zero).
+ */
+flood_status flood_filtration_backward(const flood_problem *pb, const flood_outputs *fwd,
+                                       const float *const grad_f[4], float *grad_X,
+                                       float *grad_L, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FLOOD_H */

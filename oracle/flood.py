@@ -53,9 +53,11 @@ def landmarks_in_x(X, Lxyz) -> bool:
     return bool(np.all(np.isin(Lv, Xv)))
 
 
-def flood_dim(X, Lxyz, simp, d: int, k: int, mode: str = "brute", xsorted=None, nthreads=None):
+def flood_dim(X, Lxyz, simp, d: int, k: int, mode: str = "brute", xsorted=None, nthreads=None, counter=None):
     """f_P(sigma) for the d-simplices `simp` ([n, d+1] landmark ids), without
-    the face closure.  Returns (f float64 [n], win_a int32 [n,4], win_x int32 [n])."""
+    the face closure.  Returns (f float64 [n], win_a int32 [n,4], win_x int32 [n]).
+    `counter` (int64 numpy array of one element) accumulates the number of
+    distance evaluations performed."""
     X = _as_f64(X)
     Lxyz = _as_f64(Lxyz)
     simp = np.ascontiguousarray(simp, dtype=np.int32).reshape(-1, d + 1)
@@ -72,7 +74,8 @@ def flood_dim(X, Lxyz, simp, d: int, k: int, mode: str = "brute", xsorted=None, 
     order = xsorted.order if m == 1 else np.zeros(1, np.int64)
     rc = native.lib().or_flood(native.ptr(X), X.shape[0], native.ptr(Lxyz), native.ptr(simp), n,
                                d, k, m, native.ptr(xs), native.ptr(order), native.ptr(f),
-                               native.ptr(wa), native.ptr(wx), native.threads(nthreads))
+                               native.ptr(wa), native.ptr(wx),
+                               native.ptr(counter) if counter is not None else None, native.threads(nthreads))
     if rc != 0:
         raise ValueError("or_flood failed: %d" % rc)
     return f, wa, wx
@@ -197,3 +200,37 @@ def r_exact(X, V):
                     cnt += 1
                     best = max(best, dmin)
     return best, cnt
+
+
+def diameter(X) -> float:
+    """diam(X): the largest pairwise distance, exactly over the convex-hull
+    vertices (FP64)."""
+    X = _as_f64(X)
+    if len(X) <= 3:
+        idx = np.arange(len(X))
+    else:
+        from scipy.spatial import ConvexHull
+        try:
+            idx = ConvexHull(X).vertices
+        except Exception:
+            idx = np.arange(len(X))
+    H = X[idx]
+    best = 0.0
+    for i in range(0, len(H), 512):
+        d = ((H[i:i + 512, None, :] - H[None, :, :]) ** 2).sum(-1)
+        best = max(best, float(d.max()))
+    return float(np.sqrt(best))
+
+
+def nearest(X, P):
+    """Distance from each row of P to X and the lowest-index nearest point
+    (brute force, FP64; small inputs)."""
+    X = _as_f64(X)
+    P = _as_f64(P)
+    out_d = np.empty(len(P))
+    out_i = np.empty(len(P), np.int64)
+    for i in range(0, len(P), 256):
+        d = ((P[i:i + 256, None, :] - X[None]) ** 2).sum(-1)
+        out_i[i:i + 256] = np.argmin(d, axis=1)
+        out_d[i:i + 256] = np.sqrt(d[np.arange(len(d)), out_i[i:i + 256]])
+    return out_d, out_i

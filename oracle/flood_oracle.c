@@ -150,12 +150,13 @@ static double dist2(const double *p, const double *x)
 int or_flood(const double *X, int64_t N, const double *Lxyz,
              const int32_t *simp, int64_t n, int32_t d, int32_t k,
              int32_t mode, const double *xs, const int64_t *order,
-             double *f, int32_t *win_a, int32_t *win_x, int nthreads)
+             double *f, int32_t *win_a, int32_t *win_x, int64_t *evals_out, int nthreads)
 {
     if (d < 0 || d > 3 || k < 1 || N <= 0)
         return 1;
     int rc = 0;
-#pragma omp parallel num_threads(nthreads)
+    int64_t evals = 0;
+#pragma omp parallel num_threads(nthreads) reduction(+ : evals)
     {
         int64_t *cand = NULL;
         int64_t cap = 0;
@@ -244,6 +245,7 @@ int or_flood(const double *X, int64_t N, const double *Lxyz,
                 }
                 double m2 = INFINITY;
                 int64_t mi = -1;
+                evals += nc;
                 for (int64_t t = 0; t < nc; ++t) {
                     int64_t xi = (mode == 1) ? cand[t] : t;
                     double q = dist2(p, X + 3 * xi);
@@ -274,6 +276,8 @@ int or_flood(const double *X, int64_t N, const double *Lxyz,
         }
         free(cand);
     }
+    if (evals_out)
+        *evals_out += evals;
     return rc;
 }
 

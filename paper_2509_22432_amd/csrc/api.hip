@@ -1,0 +1,153 @@
+// C ABI of libflood: argument validation (before any launch), workspace
+// queries and error reporting.  Kernels live in the .hip files.
+#include <cmath>
+#include <string>
+
+#include "internal.hpp"
+
+namespace flood_host {
+static thread_local std::string g_err;
+void set_error(const std::string &msg) { g_err = msg; }
+}  // namespace flood_host
+
+using flood_host::set_error;
+
+extern "C" const char *flood_last_error(void) { return flood_host::g_err.c_str(); }
+
+namespace {
+
+flood_status fail(flood_status st, const std::string &msg) {
+    set_error(msg);
+    return st;
+}
+
+flood_status hip_status(hipError_t e, const char *where) {
+    if (e == hipSuccess) return FLOOD_OK;
+    if (e == hipErrorOutOfMemory) return fail(FLOOD_ENOMEM, std::string(where) + ": workspace too small");
+    return fail(FLOOD_EHIP, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+bool offsets_ok(const int64_t *off, int32_t B) {
+    if (!off || off[0] != 0) return false;
+    for (int32_t b = 0; b < B; ++b)
+        if (off[b + 1] < off[b]) return false;
+    return true;
+}
+
+constexpr int64_t kMaxPoints = (int64_t)1 << 31;  // point rows travel as int32 / float bits
+
+flood_tuning default_tuning(const flood_tuning *t) {
+    flood_tuning r;
+    r.cells_per_point = 1.0f;
+    r.samples_per_lane = 1;
+    r.waves_per_block = 4;
+    r.reserved = 0;
+    if (t) {
+        if (t->cells_per_point > 0) r.cells_per_point = t->cells_per_point;
+        if (t->samples_per_lane > 0) r.samples_per_lane = t->samples_per_lane;
+        if (t->waves_per_block > 0) r.waves_per_block = t->waves_per_block;
+    }
+    return r;
+}
+
+flood_status check_tuning(const flood_tuning &t) {
+    if (!(t.cells_per_point >= 0.05f && t.cells_per_point <= 64.f))
+        return fail(FLOOD_EINVAL, "tuning: cells_per_point outside [0.05, 64]");
+    if (t.samples_per_lane != 1 && t.samples_per_lane != 2 && t.samples_per_lane != 4)
+        return fail(FLOOD_EINVAL, "tuning: samples_per_lane must be 1, 2 or 4");
+    if (t.waves_per_block < 1 || t.waves_per_block > 16) return fail(FLOOD_EINVAL, "tuning: waves_per_block outside [1, 16]");
+    return FLOOD_OK;
+}
+
+flood_status check_problem(const flood_problem *pb) {
+    if (!pb) return fail(FLOOD_EINVAL, "problem is NULL");
+    if (pb->B < 1) return fail(FLOOD_EINVAL, "problem: B must be >= 1");
+    if (pb->k < 1) return fail(FLOOD_EINVAL, "problem: k must be >= 1");
+    if (pb->k > 255) return fail(FLOOD_EUNSUPPORTED, "problem: k > 255 (compositions are packed in 8 bits)");
+    if (pb->landmarks_in_x != 0 && pb->landmarks_in_x != 1) return fail(FLOOD_EINVAL, "problem: landmarks_in_x must be 0 or 1");
+    if (!pb->X || !pb->x_off_d || !pb->Lxyz || !pb->l_off_d) return fail(FLOOD_EINVAL, "problem: NULL device pointer");
+    if (pb->landmarks_in_x && !pb->l_xidx) return fail(FLOOD_EINVAL, "problem: landmarks_in_x needs l_xidx");
+    if (!offsets_ok(pb->x_off, pb->B)) return fail(FLOOD_EINVAL, "problem: x_off must start at 0 and be non-decreasing");
+    if (!offsets_ok(pb->l_off, pb->B)) return fail(FLOOD_EINVAL, "problem: l_off must start at 0 and be non-decreasing");
+    if (pb->x_off[pb->B] >= kMaxPoints) return fail(FLOOD_EUNSUPPORTED, "problem: more than 2^31 - 1 points");
+    for (int d = 1; d < 4; ++d) {
+        if (!offsets_ok(pb->s_off[d], pb->B)) return fail(FLOOD_EINVAL, "problem: s_off must start at 0 and be non-decreasing");
+        if (pb->s_off[d][pb->B] > 0 && (!pb->simp[d] || !pb->s_off_d[d]))
+            return fail(FLOOD_EINVAL, "problem: NULL simplex array");
+        if (pb->s_off[d][pb->B] >= kMaxPoints) return fail(FLOOD_EUNSUPPORTED, "problem: too many simplices");
+    }
+    if (pb->s_off[2][pb->B] > 0 && !pb->tri_edges) return fail(FLOOD_EINVAL, "problem: tri_edges is NULL");
+    if (pb->s_off[3][pb->B] > 0 && !pb->tet_tris) return fail(FLOOD_EINVAL, "problem: tet_tris is NULL");
+    for (int32_t b = 0; b < pb->B; ++b) {
+        int64_t nsimp = pb->l_off[b + 1] - pb->l_off[b];
+        if (nsimp > 0 && pb->x_off[b + 1] == pb->x_off[b])
+            return fail(FLOOD_EINVAL, "problem: a cloud with landmarks has no points");
+    }
+    return FLOOD_OK;
+}
+
+}  // namespace
+
+extern "C" size_t flood_fps_workspace_size(int32_t B, const int64_t *x_off, const int32_t *n_lm) {
+    if (B < 1 || !offsets_ok(x_off, B) || !n_lm) return 0;
+    return flood::fps_workspace(B, x_off, n_lm);
+}
+
+extern "C" flood_status flood_fps(const float *X, int32_t B, const int64_t *x_off, const int64_t *x_off_d,
+                                  const int32_t *n_lm, const int32_t *n_lm_d, const int64_t *start_d, int32_t *idx,
+                                  float *radius, void *ws, size_t ws_bytes, void *stream) {
+    if (!X || !x_off_d || !n_lm || !n_lm_d || !idx) return fail(FLOOD_EINVAL, "flood_fps: NULL pointer");
+    if (B < 1) return fail(FLOOD_EINVAL, "flood_fps: B must be >= 1");
+    if (!offsets_ok(x_off, B)) return fail(FLOOD_EINVAL, "flood_fps: x_off must start at 0 and be non-decreasing");
+    if (x_off[B] >= kMaxPoints) return fail(FLOOD_EUNSUPPORTED, "flood_fps: more than 2^31 - 1 points");
+    for (int32_t b = 0; b < B; ++b)
+        if (n_lm[b] < 1 || n_lm[b] > x_off[b + 1] - x_off[b])
+            return fail(FLOOD_EINVAL, "flood_fps: need 1 <= n_lm[b] <= N_b");
+    size_t need = flood::fps_workspace(B, x_off, n_lm);
+    if (!ws || ws_bytes < need) return fail(FLOOD_ENOMEM, "flood_fps: workspace smaller than flood_fps_workspace_size");
+    hipError_t e = flood::fps_run(X, B, x_off, x_off_d, n_lm, n_lm_d, start_d, idx, radius, ws, ws_bytes,
+                                  (hipStream_t)stream);
+    return hip_status(e, "flood_fps");
+}
+
+extern "C" size_t flood_filtration_workspace_size(const flood_problem *pb, const flood_tuning *tune) {
+    if (check_problem(pb) != FLOOD_OK) return 0;
+    flood_tuning t = default_tuning(tune);
+    if (check_tuning(t) != FLOOD_OK) return 0;
+    return flood::flood_workspace(pb, t.cells_per_point, nullptr);
+}
+
+extern "C" flood_status flood_filtration(const flood_problem *pb, const flood_tuning *tune, const flood_outputs *out,
+                                         void *ws, size_t ws_bytes, void *stream) {
+    flood_status st = check_problem(pb);
+    if (st != FLOOD_OK) return st;
+    flood_tuning t = default_tuning(tune);
+    st = check_tuning(t);
+    if (st != FLOOD_OK) return st;
+    if (!out) return fail(FLOOD_EINVAL, "flood_filtration: outputs are NULL");
+    for (int d = 0; d < 4; ++d) {
+        int64_t n = d == 0 ? pb->l_off[pb->B] : pb->s_off[d][pb->B];
+        if (n > 0 && (!out->f[d] || !out->win_x[d] || !out->win_a[d]))
+            return fail(FLOOD_EINVAL, "flood_filtration: NULL output array");
+    }
+    size_t need = flood::flood_workspace(pb, t.cells_per_point, nullptr);
+    if (!ws || ws_bytes < need)
+        return fail(FLOOD_ENOMEM, "flood_filtration: workspace smaller than flood_filtration_workspace_size");
+    hipError_t e = flood::flood_run(pb, t, out, ws, ws_bytes, (hipStream_t)stream);
+    return hip_status(e, "flood_filtration");
+}
+
+extern "C" flood_status flood_filtration_backward(const flood_problem *pb, const flood_outputs *fwd,
+                                                  const float *const grad_f[4], float *grad_X, float *grad_L,
+                                                  void *stream) {
+    flood_status st = check_problem(pb);
+    if (st != FLOOD_OK) return st;
+    if (!fwd || !grad_f) return fail(FLOOD_EINVAL, "flood_filtration_backward: NULL argument");
+    for (int d = 0; d < 4; ++d) {
+        int64_t n = d == 0 ? pb->l_off[pb->B] : pb->s_off[d][pb->B];
+        if (n > 0 && grad_f[d] && (!fwd->win_x[d] || !fwd->win_a[d]))
+            return fail(FLOOD_EINVAL, "flood_filtration_backward: NULL winner array");
+    }
+    hipError_t e = flood::backward_run(pb, fwd, grad_f, grad_X, grad_L, (hipStream_t)stream);
+    return hip_status(e, "flood_filtration_backward");
+}

@@ -1,0 +1,302 @@
+// Uniform-grid binning of the point clouds by a device counting sort:
+// bounding box, grid parameters, per-cell histogram, exclusive scan, scatter.
+// The grid is the spatial index the flooding and landmark kernels scan; it
+// replaces the paper's presorted axis slices and Boolean masks (Sec. 4.2 and
+// its appendix) with cell lists that are contiguous in memory.
+#include "internal.hpp"
+
+namespace flood {
+
+static constexpr int kBlock = 256;
+
+__global__ void k_fill_u32(uint32_t *p, uint32_t v, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+__global__ void k_fill_u64(uint64_t *p, uint64_t v, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+__global__ void k_fill_f32(float *p, float v, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+static int grid_blocks(int64_t n) {
+    int64_t b = (n + kBlock - 1) / kBlock;
+    if (b > 65536) b = 65536;
+    if (b < 1) b = 1;
+    return (int)b;
+}
+hipError_t fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill_u32, dim3(grid_blocks(n)), dim3(kBlock), 0, s, p, v, n);
+    return hipGetLastError();
+}
+hipError_t fill_u64(uint64_t *p, uint64_t v, int64_t n, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill_u64, dim3(grid_blocks(n)), dim3(kBlock), 0, s, p, v, n);
+    return hipGetLastError();
+}
+hipError_t fill_f32(float *p, float v, int64_t n, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill_f32, dim3(grid_blocks(n)), dim3(kBlock), 0, s, p, v, n);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// exclusive scan of uint32 (3 phases; 1024 threads x 4 items per block)
+static constexpr int kScanThreads = 1024;
+static constexpr int kScanItems = 4;
+static constexpr int kScanTile = kScanThreads * kScanItems;
+
+size_t scan_tmp_elems(int64_t n) {
+    // every recursion level stores its block sums followed by 4 spare slots
+    size_t tot = 0;
+    int64_t m = n;
+    do {
+        m = (m + kScanTile - 1) / kScanTile;
+        tot += (size_t)m + 4;
+    } while (m > 1);
+    return tot + 64;
+}
+
+__device__ inline uint32_t block_exclusive_scan(uint32_t v, uint32_t *total) {
+    __shared__ uint32_t warp_sums[kScanThreads / 64];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    uint32_t x = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        uint32_t y = __shfl_up(x, o, 64);
+        if (lane >= o) x += y;
+    }
+    if (lane == 63) warp_sums[wid] = x;
+    __syncthreads();
+    if (wid == 0) {
+        uint32_t w = lane < kScanThreads / 64 ? warp_sums[lane] : 0u;
+        uint32_t z = w;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            uint32_t y = __shfl_up(z, o, 64);
+            if (lane >= o) z += y;
+        }
+        if (lane < kScanThreads / 64) warp_sums[lane] = z - w;
+        if (lane == kScanThreads / 64 - 1) *total = z;
+    }
+    __syncthreads();
+    uint32_t r = warp_sums[wid] + x - v;
+    __syncthreads();
+    return r;
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_local(uint32_t *d, int64_t n, uint32_t *block_sums) {
+    __shared__ uint32_t tot;
+    int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+    uint32_t v[kScanItems];
+    uint32_t s = 0;
+#pragma unroll
+    for (int i = 0; i < kScanItems; ++i) {
+        v[i] = (base + i < n) ? d[base + i] : 0u;
+        s += v[i];
+    }
+    uint32_t off = block_exclusive_scan(s, &tot);
+#pragma unroll
+    for (int i = 0; i < kScanItems; ++i) {
+        if (base + i < n) d[base + i] = off;
+        off += v[i];
+    }
+    if (threadIdx.x == 0) block_sums[blockIdx.x] = tot;
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_add(uint32_t *d, int64_t n, const uint32_t *block_off) {
+    int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+    uint32_t a = block_off[blockIdx.x];
+#pragma unroll
+    for (int i = 0; i < kScanItems; ++i)
+        if (base + i < n) d[base + i] += a;
+}
+
+hipError_t exclusive_scan_u32(uint32_t *data, int64_t n, uint32_t *tmp, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    int64_t nb = (n + kScanTile - 1) / kScanTile;
+    uint32_t *sums = tmp;
+    uint32_t *sums2 = tmp + nb + 4;
+    hipLaunchKernelGGL(k_scan_local, dim3((unsigned)nb), dim3(kScanThreads), 0, s, data, n, sums);
+    if (nb > 1) {
+        hipError_t e = exclusive_scan_u32(sums, nb, sums2, s);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(k_scan_add, dim3((unsigned)nb), dim3(kScanThreads), 0, s, data, n, sums);
+    }
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// grid build
+
+size_t grid_workspace(int32_t B, const int64_t *x_off, float alpha, int64_t *total_cells) {
+    int64_t tc = 0;
+    for (int32_t b = 0; b < B; ++b) tc += cells_cap(x_off[b + 1] - x_off[b], alpha);
+    if (total_cells) *total_cells = tc;
+    int64_t np = x_off[B];
+    size_t bytes = 0;
+    bytes += sizeof(GridParam) * B + 256;
+    bytes += sizeof(uint32_t) * 6 * B + 256;
+    bytes += sizeof(float4) * np + 256;
+    bytes += sizeof(uint32_t) * np + 256;
+    bytes += sizeof(uint32_t) * (tc + 1) + 256;
+    bytes += sizeof(uint32_t) * tc + 256;
+    bytes += sizeof(uint32_t) * scan_tmp_elems(tc + 1) + 256;
+    return bytes;
+}
+
+void grid_carve(Carve &c, int32_t B, int64_t total_pts, int64_t total_cells, GridWork &g) {
+    g.gp = c.take<GridParam>(B);
+    g.bbox = c.take<uint32_t>(6 * (size_t)B);
+    g.xs = c.take<float4>(total_pts);
+    g.pcell = c.take<uint32_t>(total_pts);
+    g.cell_start = c.take<uint32_t>(total_cells + 1);
+    g.cursor = c.take<uint32_t>(total_cells);
+    g.scan_tmp = c.take<uint32_t>(scan_tmp_elems(total_cells + 1));
+    g.total_cells = total_cells;
+    g.total_pts = total_pts;
+}
+
+__global__ void k_bbox_init(uint32_t *bbox, int32_t B) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < 6 * B) bbox[i] = (i % 6) < 3 ? 0xffffffffu : 0u;
+}
+
+// gridDim.y = cloud; each block reduces a contiguous part of the cloud
+__global__ __launch_bounds__(kBlock) void k_bbox(const float *X, const int64_t *x_off, uint32_t *bbox) {
+    const int b = blockIdx.y;
+    const int64_t lo = x_off[b], hi = x_off[b + 1];
+    float mn[3] = {INFINITY, INFINITY, INFINITY}, mx[3] = {-INFINITY, -INFINITY, -INFINITY};
+    for (int64_t i = lo + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < hi; i += (int64_t)gridDim.x * blockDim.x) {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            float v = X[3 * i + a];
+            mn[a] = fminf(mn[a], v);
+            mx[a] = fmaxf(mx[a], v);
+        }
+    }
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            mn[a] = fminf(mn[a], __shfl_xor(mn[a], o, 64));
+            mx[a] = fmaxf(mx[a], __shfl_xor(mx[a], o, 64));
+        }
+    }
+    if ((threadIdx.x & 63) == 0 && lo < hi) {
+        for (int a = 0; a < 3; ++a) {
+            if (mn[a] <= mx[a]) {
+                atomicMin(&bbox[6 * b + a], float_key(mn[a]));
+                atomicMax(&bbox[6 * b + 3 + a], float_key(mx[a]));
+            }
+        }
+    }
+}
+
+// one thread: grid parameters of every cloud (sequential prefix of the cell bases)
+__global__ void k_grid_params(const uint32_t *bbox, const int64_t *x_off, int32_t B, float alpha, GridParam *gp) {
+    if (blockIdx.x != 0 || threadIdx.x != 0) return;
+    int64_t base = 0;
+    for (int32_t b = 0; b < B; ++b) {
+        GridParam g;
+        int64_t n = x_off[b + 1] - x_off[b];
+        int64_t cap = cells_cap(n, alpha);
+        float lo[3], hi[3], e[3];
+        float emax = 0.f, amax = 0.f;
+        for (int a = 0; a < 3; ++a) {
+            lo[a] = key_float(bbox[6 * b + a]);
+            hi[a] = key_float(bbox[6 * b + 3 + a]);
+            if (!(lo[a] <= hi[a])) { lo[a] = 0.f; hi[a] = 0.f; }  // empty cloud or non-finite data
+            e[a] = hi[a] - lo[a];
+            emax = fmaxf(emax, e[a]);
+            amax = fmaxf(amax, fmaxf(fabsf(lo[a]), fabsf(hi[a])));
+        }
+        if (!(emax > 0.f)) emax = 1.f;
+        double target = (double)(cap - 64) > 1.0 ? (double)(cap - 64) : 1.0;
+        double vol = 1.0;
+        for (int a = 0; a < 3; ++a) vol *= fmax((double)e[a], 1e-7 * (double)emax);
+        double h = cbrt(vol / target);
+        if (!(h > 0.0)) h = emax;
+        int64_t nx, ny, nz;
+        for (int it = 0; it < 4096; ++it) {
+            nx = (int64_t)floor((double)e[0] / h) + 1;
+            ny = (int64_t)floor((double)e[1] / h) + 1;
+            nz = (int64_t)floor((double)e[2] / h) + 1;
+            if (nx <= (1 << 20) && ny <= (1 << 20) && nz <= (1 << 20) && nx * ny * nz <= cap) break;
+            h *= 1.05;
+        }
+        g.ox = lo[0]; g.oy = lo[1]; g.oz = lo[2];
+        g.h = (float)h;
+        g.inv_h = (float)(1.0 / h);
+        g.eps = 1e-3f * (float)h + 1e-6f * amax;
+        g.nx = (int32_t)nx; g.ny = (int32_t)ny; g.nz = (int32_t)nz;
+        g.pad = 0;
+        g.cell_base = base;
+        g.pt_base = x_off[b];
+        g.npts = n;
+        g.cells_cap = cap;
+        gp[b] = g;
+        base += cap;
+    }
+}
+
+__device__ inline int cell_coord(float v, float o, float inv_h, int n) {
+    float t = (v - o) * inv_h;
+    int c = (t >= 0.f) ? (int)t : 0;   // also maps NaN to 0
+    return c < n ? c : n - 1;
+}
+
+__global__ __launch_bounds__(kBlock) void k_count(const float *X, const GridParam *gp, uint32_t *pcell, uint32_t *counts) {
+    const int b = blockIdx.y;
+    const GridParam g = gp[b];
+    const int64_t lo = g.pt_base, hi = g.pt_base + g.npts;
+    for (int64_t i = lo + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < hi; i += (int64_t)gridDim.x * blockDim.x) {
+        int cx = cell_coord(X[3 * i], g.ox, g.inv_h, g.nx);
+        int cy = cell_coord(X[3 * i + 1], g.oy, g.inv_h, g.ny);
+        int cz = cell_coord(X[3 * i + 2], g.oz, g.inv_h, g.nz);
+        uint32_t c = (uint32_t)(g.cell_base + ((int64_t)cz * g.ny + cy) * g.nx + cx);
+        pcell[i] = c;
+        atomicAdd(&counts[c], 1u);
+    }
+}
+
+__global__ void k_copy_u32(const uint32_t *src, uint32_t *dst, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        dst[i] = src[i];
+}
+
+__global__ __launch_bounds__(kBlock) void k_scatter(const float *X, const GridParam *gp, const uint32_t *pcell,
+                                                     uint32_t *cursor, float4 *xs) {
+    const int b = blockIdx.y;
+    const GridParam g = gp[b];
+    const int64_t lo = g.pt_base, hi = g.pt_base + g.npts;
+    for (int64_t i = lo + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < hi; i += (int64_t)gridDim.x * blockDim.x) {
+        uint32_t pos = atomicAdd(&cursor[pcell[i]], 1u);
+        xs[pos] = make_float4(X[3 * i], X[3 * i + 1], X[3 * i + 2], __int_as_float((int)i));
+    }
+}
+
+hipError_t grid_build(const float *X, int32_t B, const int64_t *x_off, const int64_t *x_off_d,
+                      float alpha, GridWork &g, hipStream_t s) {
+    int64_t nmax = 0;
+    for (int32_t b = 0; b < B; ++b) nmax = nmax > x_off[b + 1] - x_off[b] ? nmax : x_off[b + 1] - x_off[b];
+    int bx = (int)((nmax + kBlock * 8 - 1) / (kBlock * 8));
+    if (bx < 1) bx = 1;
+    if (bx > 4096) bx = 4096;
+    hipLaunchKernelGGL(k_bbox_init, dim3((6 * B + 255) / 256), dim3(256), 0, s, g.bbox, B);
+    hipLaunchKernelGGL(k_bbox, dim3(bx, B), dim3(kBlock), 0, s, X, x_off_d, g.bbox);
+    hipLaunchKernelGGL(k_grid_params, dim3(1), dim3(1), 0, s, g.bbox, x_off_d, B, alpha, g.gp);
+    hipError_t e = fill_u32(g.cell_start, 0u, g.total_cells + 1, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_count, dim3(bx, B), dim3(kBlock), 0, s, X, g.gp, g.pcell, g.cell_start);
+    e = exclusive_scan_u32(g.cell_start, g.total_cells + 1, g.scan_tmp, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_copy_u32, dim3(grid_blocks(g.total_cells)), dim3(kBlock), 0, s, g.cell_start, g.cursor, g.total_cells);
+    hipLaunchKernelGGL(k_scatter, dim3(bx, B), dim3(kBlock), 0, s, X, g.gp, g.pcell, g.cursor, g.xs);
+    return hipGetLastError();
+}
+
+}  // namespace flood

@@ -1,0 +1,71 @@
+"""GPU backward against the oracle's analytic gradient (FP64), with the
+near-tie simplices (where several winners are correct) given zero weight."""
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import flood as OF
+
+from gpu_helpers import oracle_complex, run_single
+
+pytestmark = pytest.mark.gpu
+
+
+def _tie_gap(X, L, simp, d, k):
+    S = OF.samples(d, k) / k
+    V = L[simp].astype(np.float64)
+    P = np.einsum("sd,ndc->nsc", S, V)
+    gaps = np.empty(len(V))
+    for i in range(len(V)):
+        dist = np.sqrt(((P[i][:, None, :] - X[None].astype(np.float64)) ** 2).sum(-1))
+        part = np.sort(dist, axis=1)
+        nn = part[:, 0]
+        order = np.sort(nn)
+        g1 = order[-1] - order[-2] if len(order) > 1 else np.inf
+        b = np.argmax(nn)
+        gaps[i] = min(g1, part[b, 1] - part[b, 0])
+    return gaps
+
+
+def test_backward_matches_oracle_gradient():
+    X = synth.differentiable_clouds(1, 3000, seed=5)[0]
+    k = 6
+    res = run_single(X, 48, k)
+    cx = oracle_complex(res["cx"])
+    Lx = res["Lxyz"]
+    diam = OF.diameter(X)
+    rng = np.random.default_rng(1)
+    vals = OF.flood_all(X, Lx, cx, k, "brute")
+    w = {}
+    for d in range(4):
+        w[d] = rng.random(len(vals[d][0]))
+        if d > 0:
+            simp = cx[{1: "E", 2: "F", 3: "T"}[d]]
+            w[d][_tie_gap(X, Lx, simp, d, k) <= 1e-4 * diam] = 0.0
+    gX_ref, gL_ref = OF.gradient(X, Lx, cx, vals, k, w)
+    run = res["run"]
+    gX = torch.zeros_like(run.pb.X)
+    gL = torch.zeros_like(run.pb.Lxyz)
+    run.backward([torch.from_numpy(w[d].astype(np.float32)).to(gX.device) for d in range(4)], gX, gL)
+    torch.cuda.synchronize()
+    gX, gL = gX.cpu().numpy(), gL.cpu().numpy()
+    assert np.abs(gX - gX_ref).max() <= 1e-4 * (1 + np.abs(gX_ref).max())
+    assert np.abs(gL - gL_ref).max() <= 1e-4 * (1 + np.abs(gL_ref).max())
+
+
+def test_autograd_function_routes_gradients():
+    import paper_2509_22432_amd as P
+    X = synth.differentiable_clouds(1, 2000, seed=9)[0]
+    res = run_single(X, 32, 4)
+    pb = res["pb"]
+    Xg = pb.X.requires_grad_(True)
+    Lg = pb.Lxyz.requires_grad_(True)
+    f = P.FloodFiltration.apply(Xg, Lg, pb)
+    loss = sum((t * (i + 1)).sum() for i, t in enumerate(f))
+    loss.backward()
+    gX = torch.zeros_like(pb.X)
+    gL = torch.zeros_like(pb.Lxyz)
+    res["run"].backward([torch.full_like(res["run"].f[d], d + 1.0) for d in range(4)], gX, gL)
+    torch.cuda.synchronize()
+    assert torch.allclose(Xg.grad, gX, atol=1e-5) and torch.allclose(Lg.grad, gL, atol=1e-5)
