@@ -88,6 +88,8 @@ def main():
     ap.add_argument("--tuning", type=str, default=None, help="JSON dict of flood_tuning fields")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--batched-clouds", type=int, default=512, help="0 skips the batched block")
+    ap.add_argument("--batched-scale", type=float, default=1.0)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the flooding path here is single-GPU "
@@ -125,6 +127,7 @@ def main():
         P.fps(Xd, args.n_landmarks)
         s1.record()
         run.evals.zero_()
+        run.stats.zero_()
         run()
 
     for _ in range(args.warmup):
@@ -174,6 +177,9 @@ def main():
                    "tuning": tuning},
         "simplices_per_s": nsimp / (ms * 1e-3),
         "evals_per_step": ev,
+        "search_stats_per_dim": {"per_sample_search_samples": [int(v) for v in run.stats.view(4, 4)[:, 1].cpu()],
+                                 "tile_evals": [int(v) for v in run.stats.view(4, 4)[:, 2].cpu()],
+                                 "per_sample_evals": [int(v) for v in run.stats.view(4, 4)[:, 3].cpu()]},
         "stage_ms": {"fps": float(np.mean(fps_ms)), "filtration": float(np.mean(flood_ms)),
                      "flood_search_per_dim": [float(np.mean([t[d] for t in tile_ms])) for d in range(4)],
                      "delaunay_host_once": del_ms},
@@ -184,7 +190,68 @@ def main():
     if not args.no_cpu_baseline:
         print("bench: cpu baseline (oracle) ...", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(X, Lxyz, cx, args.k, args.cpu_seconds)
+    if args.batched_clouds > 0:
+        del run, pb, Xd, Ld
+        torch.cuda.empty_cache()
+        out["batched"] = batched_block(args.batched_clouds, args.batched_scale, max(args.steps, 3))
     print(json.dumps(out), flush=True)
+
+
+def batched_block(n_clouds, scale, reps):
+    """Workload 'batch512': clouds/s of the batched filtration (one HIP graph
+    replay) against the same clouds run one plain call at a time."""
+    import torch
+    import synth
+    from paper_2509_22432_amd import api, batch
+    t0 = time.time()
+    clouds, lms = synth.batched_clouds(n_clouds, scale=scale)
+    print("bench: batched: %d clouds, %d points generated in %.1fs" % (len(clouds), sum(map(len, clouds)),
+                                                                      time.time() - t0), file=sys.stderr, flush=True)
+    t0 = time.time()
+    pb, Ls, cxs = batch.prepare(clouds, lms, 6)
+    prep_s = time.time() - t0
+    gf = batch.GraphedFiltration(pb)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    times = []
+    for _ in range(reps):
+        gf.run.evals.zero_()
+        gf.run.stats.zero_()
+        e0.record()
+        gf.replay()
+        e1.record()
+        torch.cuda.synchronize()
+        times.append(e0.elapsed_time(e1))
+    g_ms = float(np.median(times))
+    evals = int(gf.run.evals.item())
+    # the same clouds as separate plain calls (one problem per cloud)
+    singles = []
+    for b in range(len(clouds)):
+        xo = [0, len(clouds[b])]
+        Xb = torch.from_numpy(clouds[b]).cuda()
+        Lb = torch.from_numpy(Ls[b]).cuda()
+        li = pb.l_xidx[int(pb.l_off[b]):int(pb.l_off[b + 1])] - int(pb.x_off[b])
+        p1 = api.problem_from_complexes(Xb, xo, Lb, [0, len(Ls[b])], [cxs[b]], 6, l_xidx=li.contiguous())
+        singles.append(api.FloodRun(p1, None, count_evals=False))
+    for r in singles:
+        r()
+    torch.cuda.synchronize()
+    e0.record()
+    for r in singles:
+        r()
+    e1.record()
+    torch.cuda.synchronize()
+    plain_ms = e0.elapsed_time(e1)
+    V = int(pb.l_off[-1])
+    n_simp = V + sum(pb.n(d) for d in (1, 2, 3))
+    return {"workload": "batch512: %d clouds, N log-uniform in [1e4, 5e5] x %.2f, 1-6 primitives, L = min(N/100, 4096), k=6"
+                        % (len(clouds), scale),
+            "clouds_per_s": len(clouds) / (g_ms * 1e-3), "graph_replay_ms": g_ms,
+            "plain_per_cloud_calls_ms": plain_ms, "plain_clouds_per_s": len(clouds) / (plain_ms * 1e-3),
+            "points": int(pb.x_off[-1]), "landmarks": V, "simplices": n_simp, "evals": evals,
+            "search_stats_per_dim": {"per_sample_search_samples": [int(v) for v in gf.run.stats.view(4, 4)[:, 1].cpu()],
+                                     "tile_evals": [int(v) for v in gf.run.stats.view(4, 4)[:, 2].cpu()],
+                                     "per_sample_evals": [int(v) for v in gf.run.stats.view(4, 4)[:, 3].cpu()]},
+            "host_prepare_s (fps + delaunay, untimed)": prep_s}
 
 
 if __name__ == "__main__":

@@ -157,23 +157,30 @@ typedef struct {
  * distance evaluations executed for live samples.
  * tile_events: optional caller-created hipEvent_t handles; entries 2d and
  * 2d+1 are recorded on `stream` right before and after the flooding-search
- * kernel of dimension d (NULL entries are skipped).  For profiling only. */
+ * kernels of dimension d (NULL entries are skipped).  For profiling only.
+ * stats: device uint64 [16] or NULL; receives (+=), for dimension d,
+ * [4d+1] samples handed to the per-sample search, [4d+2] evaluations in the
+ * cooperative tile search, [4d+3] evaluations in the per-sample search. */
 typedef struct {
     float *f[4];
     int32_t *win_x[4];
     uint32_t *win_a[4];
     uint64_t *evals;
     void *tile_events[8];
+    uint64_t *stats;
 } flood_outputs;
 
-/* Tuning knobs; pass NULL for the defaults.  They change speed, never the
- * values: cells_per_point (target uniform-grid cells per point, 0.05..64),
- * samples_per_lane (1..4), waves_per_block (1..16). */
+/* Tuning knobs; pass NULL for the defaults (a zero field also selects its
+ * default).  They change speed, never the values: cells_per_point (target
+ * uniform-grid cells per point, 0.05..64), samples_per_lane (1, 2 or 4),
+ * waves_per_block (1..16), tile_shells (cell shells a wave scans
+ * cooperatively around its samples before handing open samples to the
+ * per-lane search, 1..8; -1 sends every sample to the per-lane search). */
 typedef struct {
     float cells_per_point;
     int32_t samples_per_lane;
     int32_t waves_per_block;
-    int32_t reserved;
+    int32_t tile_shells;
 } flood_tuning;
 
 size_t flood_filtration_workspace_size(const flood_problem *pb, const flood_tuning *tune);

@@ -53,11 +53,14 @@ def landmarks_in_x(X, Lxyz) -> bool:
     return bool(np.all(np.isin(Lv, Xv)))
 
 
-def flood_dim(X, Lxyz, simp, d: int, k: int, mode: str = "brute", xsorted=None, nthreads=None, counter=None):
+def flood_dim(X, Lxyz, simp, d: int, k: int, mode: str = "brute", xsorted=None, nthreads=None, counter=None,
+              gaps=False):
     """f_P(sigma) for the d-simplices `simp` ([n, d+1] landmark ids), without
     the face closure.  Returns (f float64 [n], win_a int32 [n,4], win_x int32 [n]).
     `counter` (int64 numpy array of one element) accumulates the number of
-    distance evaluations performed."""
+    distance evaluations performed.  With gaps=True also returns
+    (gap between the two best samples, gap between the two nearest points at
+    the best sample) per simplex."""
     X = _as_f64(X)
     Lxyz = _as_f64(Lxyz)
     simp = np.ascontiguousarray(simp, dtype=np.int32).reshape(-1, d + 1)
@@ -65,8 +68,10 @@ def flood_dim(X, Lxyz, simp, d: int, k: int, mode: str = "brute", xsorted=None, 
     f = np.zeros(n, np.float64)
     wa = np.zeros((n, 4), np.int32)
     wx = np.zeros(n, np.int32)
+    gs = np.zeros(n, np.float64)
+    gx = np.zeros(n, np.float64)
     if n == 0:
-        return f, wa, wx
+        return (f, wa, wx, gs, gx) if gaps else (f, wa, wx)
     m = {"brute": 0, "masked": 1}[mode]
     if m == 1 and xsorted is None:
         xsorted = XSorted(X)
@@ -75,10 +80,12 @@ def flood_dim(X, Lxyz, simp, d: int, k: int, mode: str = "brute", xsorted=None, 
     rc = native.lib().or_flood(native.ptr(X), X.shape[0], native.ptr(Lxyz), native.ptr(simp), n,
                                d, k, m, native.ptr(xs), native.ptr(order), native.ptr(f),
                                native.ptr(wa), native.ptr(wx),
-                               native.ptr(counter) if counter is not None else None, native.threads(nthreads))
+                               native.ptr(counter) if counter is not None else None,
+                               native.ptr(gs) if gaps else None, native.ptr(gx) if gaps else None,
+                               native.threads(nthreads))
     if rc != 0:
         raise ValueError("or_flood failed: %d" % rc)
-    return f, wa, wx
+    return (f, wa, wx, gs, gx) if gaps else (f, wa, wx)
 
 
 def flood_all(X, Lxyz, cx, k: int, mode: str = "brute", nthreads=None):

@@ -103,6 +103,11 @@ int or_fps(const float *X, int64_t N, int64_t start, int32_t L,
  * (k,0,..,0); the winner a* is the first sample attaining the maximum, and x*
  * the lowest index attaining the minimum.
  *
+ * gap_s / gap_x (optional): the gap between the best and second-best sample
+ * value, and at the best sample between its nearest and second-nearest
+ * point -- small gaps mark simplices whose winner is nearly tied (in masked
+ * mode the second-nearest point is taken within the mask).
+ *
  * mode 0 (brute): min over all of X.
  * mode 1 (masked): min over X cap B(c, rho) with c the midpoint of the
  *   longest edge, r = max_i ||c - v_i|| and rho = sqrt(2) r (rho = r for an
@@ -150,7 +155,8 @@ static double dist2(const double *p, const double *x)
 int or_flood(const double *X, int64_t N, const double *Lxyz,
              const int32_t *simp, int64_t n, int32_t d, int32_t k,
              int32_t mode, const double *xs, const int64_t *order,
-             double *f, int32_t *win_a, int32_t *win_x, int64_t *evals_out, int nthreads)
+             double *f, int32_t *win_a, int32_t *win_x, int64_t *evals_out, double *gap_s,
+             double *gap_x, int nthreads)
 {
     if (d < 0 || d > 3 || k < 1 || N <= 0)
         return 1;
@@ -232,7 +238,7 @@ int or_flood(const double *X, int64_t N, const double *Lxyz,
             int a[4] = {0, 0, 0, 0};
             a[0] = k;
             int done = 0;
-            double fbest = -1.0;
+            double fbest = -1.0, fsecond = -1.0, xgap = INFINITY;
             int abest[4] = {0, 0, 0, 0};
             int64_t xbest = -1;
             while (!done) {
@@ -243,15 +249,18 @@ int or_flood(const double *X, int64_t N, const double *Lxyz,
                     p[1] += w * v[i][1];
                     p[2] += w * v[i][2];
                 }
-                double m2 = INFINITY;
+                double m2 = INFINITY, m2b = INFINITY;  /* nearest and second nearest */
                 int64_t mi = -1;
                 evals += nc;
                 for (int64_t t = 0; t < nc; ++t) {
                     int64_t xi = (mode == 1) ? cand[t] : t;
                     double q = dist2(p, X + 3 * xi);
                     if (q < m2 || (q == m2 && xi < mi)) {
+                        m2b = m2;
                         m2 = q;
                         mi = xi;
+                    } else if (q < m2b) {
+                        m2b = q;
                     }
                 }
                 double dist = sqrt(m2);
@@ -260,16 +269,24 @@ int or_flood(const double *X, int64_t N, const double *Lxyz,
                     rc = 5; /* empty candidate set: mask precondition violated */
                 }
                 if (dist > fbest) {
+                    fsecond = fbest;
                     fbest = dist;
                     xbest = mi;
+                    xgap = sqrt(m2b) - dist;
                     for (int i = 0; i < 4; ++i)
                         abest[i] = a[i];
+                } else if (dist > fsecond) {
+                    fsecond = dist;
                 }
                 if (d == 0)
                     break;
                 next_composition_desc(a, d, &done);
             }
             f[s] = fbest;
+            if (gap_s)
+                gap_s[s] = fsecond < 0.0 ? INFINITY : fbest - fsecond;
+            if (gap_x)
+                gap_x[s] = xgap;
             win_x[s] = (int32_t)xbest;
             for (int i = 0; i < 4; ++i)
                 win_a[4 * s + i] = abest[i];

@@ -21,7 +21,7 @@ def lib():
         L.or_flood.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
                                ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                                ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
-                               ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int]
+                               ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int]
         L.or_max_threads.restype = ctypes.c_int
         L.or_count_samples.restype = ctypes.c_int64
         L.or_count_samples.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p]

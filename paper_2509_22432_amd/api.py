@@ -218,6 +218,7 @@ def _tuning(tuning):
     t.cells_per_point = float(tuning.get("cells_per_point", 0.0))
     t.samples_per_lane = int(tuning.get("samples_per_lane", 0))
     t.waves_per_block = int(tuning.get("waves_per_block", 0))
+    t.tile_shells = int(tuning.get("tile_shells", 0))
     return t
 
 
@@ -233,12 +234,14 @@ class FloodRun:
         self.win_x = [torch.empty(pb.n(d), dtype=torch.int32, device=dev) for d in range(4)]
         self.win_a = [torch.empty(pb.n(d), dtype=torch.int32, device=dev) for d in range(4)]
         self.evals = torch.zeros(1, dtype=torch.int64, device=dev) if count_evals else None
+        self.stats = torch.zeros(16, dtype=torch.int64, device=dev) if count_evals else None
         o = Outputs()
         for d in range(4):
             o.f[d] = self.f[d].data_ptr() if self.f[d].numel() else None
             o.win_x[d] = self.win_x[d].data_ptr() if self.win_x[d].numel() else None
             o.win_a[d] = self.win_a[d].data_ptr() if self.win_a[d].numel() else None
         o.evals = self.evals.data_ptr() if self.evals is not None else None
+        o.stats = self.stats.data_ptr() if self.stats is not None else None
         self.out = o
         tp = ctypes.byref(self.tuning) if self.tuning is not None else None
         self.ws_bytes = lib().flood_filtration_workspace_size(ctypes.byref(pb.struct()), tp)

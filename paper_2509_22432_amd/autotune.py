@@ -1,0 +1,94 @@
+"""Autotuner for the flooding search.
+
+Tuning never changes the values (exact pruning only; the GPU tests check
+bit-identical f and winners across tunings), so the fastest candidate is
+always a valid choice.  Candidates are timed on the real problem with HIP
+events; the winner is cached in a JSON file keyed by device architecture,
+CU count, point / landmark buckets (powers of two), k and cloud count.
+"""
+from __future__ import annotations
+
+import json
+import math
+import os
+
+import torch
+
+from . import api
+
+DEFAULT_CANDIDATES = [
+    {"cells_per_point": 1.0, "samples_per_lane": 1, "waves_per_block": 4, "tile_shells": 2},
+    {"cells_per_point": 0.5, "samples_per_lane": 1, "waves_per_block": 4, "tile_shells": 2},
+    {"cells_per_point": 2.0, "samples_per_lane": 1, "waves_per_block": 4, "tile_shells": 2},
+    {"cells_per_point": 1.0, "samples_per_lane": 2, "waves_per_block": 4, "tile_shells": 2},
+    {"cells_per_point": 1.0, "samples_per_lane": 1, "waves_per_block": 4, "tile_shells": 1},
+    {"cells_per_point": 1.0, "samples_per_lane": 1, "waves_per_block": 4, "tile_shells": 3},
+    {"cells_per_point": 1.0, "samples_per_lane": 1, "waves_per_block": 4, "tile_shells": -1},
+]
+
+
+def cache_path():
+    return os.environ.get("FLOOD_AUTOTUNE_CACHE",
+                          os.path.join(os.path.expanduser("~"), ".cache", "flood_mi355x_autotune.json"))
+
+
+def problem_key(pb: api.FloodProblem) -> str:
+    props = torch.cuda.get_device_properties(pb.X.device)
+    npts = int(pb.x_off[-1])
+    nl = int(pb.l_off[-1])
+    b2 = lambda v: int(round(math.log2(max(v, 1))))
+    return "%s|cu%d|N2^%d|L2^%d|k%d|B%d" % (getattr(props, "gcnArchName", props.name), props.multi_processor_count,
+                                          b2(npts), b2(nl), pb.k, b2(pb.B))
+
+
+def _load():
+    try:
+        with open(cache_path()) as f:
+            return json.load(f)
+    except (OSError, ValueError):
+        return {}
+
+
+def _store(cache):
+    path = cache_path()
+    os.makedirs(os.path.dirname(path), exist_ok=True)
+    tmp = path + ".tmp%d" % os.getpid()
+    with open(tmp, "w") as f:
+        json.dump(cache, f, indent=1, sort_keys=True)
+    os.replace(tmp, path)
+
+
+def time_tuning(pb: api.FloodProblem, tuning, reps: int = 2) -> float:
+    run = api.FloodRun(pb, tuning, count_evals=False)
+    run()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    best = float("inf")
+    for _ in range(reps):
+        e0.record()
+        run()
+        e1.record()
+        torch.cuda.synchronize()
+        best = min(best, e0.elapsed_time(e1))
+    del run
+    return best
+
+
+def autotune(pb: api.FloodProblem, candidates=None, use_cache: bool = True, verbose: bool = False):
+    """Returns (best tuning dict, {str(tuning): ms})."""
+    key = problem_key(pb)
+    cache = _load() if use_cache else {}
+    if use_cache and key in cache:
+        return cache[key]["tuning"], cache[key].get("timings", {})
+    timings = {}
+    best, best_ms = None, float("inf")
+    for cand in candidates or DEFAULT_CANDIDATES:
+        ms = time_tuning(pb, cand)
+        timings[json.dumps(cand, sort_keys=True)] = ms
+        if verbose:
+            print("autotune %s: %.3f ms" % (cand, ms))
+        if ms < best_ms:
+            best, best_ms = cand, ms
+    if use_cache:
+        cache[key] = {"tuning": best, "ms": best_ms, "timings": timings}
+        _store(cache)
+    return best, timings

@@ -63,20 +63,39 @@ __global__ void k_seed(int d, int64_t n, const int32_t *__restrict__ simp1, cons
 __device__ __forceinline__ float key_value(uint64_t kv) { return __uint_as_float((uint32_t)(kv >> 32)); }
 
 // ---------------------------------------------------------------------------
-// the tile kernel
+// phase A: cooperative tile scan (compact tiles, bounded radius)
 
 struct TileArgs {
     int32_t d, k, n_int, landmarks_in_x;
-    int32_t B, pad;
+    int32_t B, radius_budget;  // shells scanned beyond the samples' own cells
+    int32_t max_extent;        // tiles whose samples span more cells go straight to phase B
+    int32_t pad;
     int64_t n_tiles;
 };
 
+__device__ __forceinline__ float box_lb2(float sx, float sy, float sz, float bx0, float bx1, float by0, float by1,
+                                         float bz0, float bz1) {
+    const float ex = fmaxf(fmaxf(bx0 - sx, sx - bx1), 0.f);
+    const float ey = fmaxf(fmaxf(by0 - sy, sy - by1), 0.f);
+    const float ez = fmaxf(fmaxf(bz0 - sz, sz - bz1), 0.f);
+    return ex * ex + ey * ey + ez * ez;
+}
+
+__device__ __forceinline__ void publish(uint64_t *key, const float *seed, int32_t j, int32_t q, float best) {
+    const float v = __fsqrt_rn(best);
+    if (v > seed[j]) {
+        const uint64_t nk = ((uint64_t)__float_as_uint(v) << 32) | (uint64_t)(0xffffffffu - (uint32_t)q);
+        atomicMax((unsigned long long *)&key[j], (unsigned long long)nk);
+    }
+}
+
 template <int T>
 __global__ __launch_bounds__(kWaveBlock) void k_flood_tiles(
-    TileArgs a, const float *__restrict__ L, const int32_t *__restrict__ lxidx, const int32_t *__restrict__ simp,
-    const int64_t *__restrict__ s_off, const int64_t *__restrict__ tile_off, const float *__restrict__ seed,
-    uint64_t *__restrict__ key, const GridParam *__restrict__ gp, const uint32_t *__restrict__ cs,
-    const float4 *__restrict__ xs, unsigned long long *__restrict__ evals) {
+    TileArgs a, const float *__restrict__ L, const int32_t *__restrict__ simp, const int64_t *__restrict__ s_off,
+    const int64_t *__restrict__ tile_off, const float *__restrict__ seed, uint64_t *__restrict__ key,
+    const GridParam *__restrict__ gp, const uint32_t *__restrict__ cs, const float4 *__restrict__ xs,
+    uint64_t *__restrict__ hard, uint32_t *__restrict__ hard_count, unsigned long long *__restrict__ evals,
+    unsigned long long *__restrict__ stats) {
     const int lane = threadIdx.x & 63;
     const int wpb = blockDim.x >> 6;
     // wave-uniform by construction; readfirstlane lets the compiler keep the
@@ -98,27 +117,25 @@ __global__ __launch_bounds__(kWaveBlock) void k_flood_tiles(
 
     float sx[T], sy[T], sz[T], best[T], M[T];
     int32_t sj[T], sq[T];
-    bool valid[T], live[T];
+    bool live[T], cand[T];
 #pragma unroll
     for (int t = 0; t < T; ++t) {
         const int64_t ls = ls0 + (int64_t)t * 64 + lane;
-        valid[t] = ls < S;
+        const bool valid = ls < S;
+        cand[t] = false;
         sx[t] = sy[t] = sz[t] = 0.f;
         best[t] = 0.f;
         M[t] = 0.f;
         sj[t] = 0;
         sq[t] = 0;
-        if (valid[t]) {
+        if (valid) {
             const int64_t j = sbase + ls / a.n_int;
             const int q = (int)(ls % a.n_int);
             sj[t] = (int32_t)j;
             sq[t] = q;
             int comp[4];
-            if (d == 0) {
-                comp[0] = a.k;
-            } else {
-                unrank_interior(q, d, a.k, comp);
-            }
+            if (d == 0) comp[0] = a.k;
+            else unrank_interior(q, d, a.k, comp);
             int32_t v[4];
             simplex_vertices(simp, d, j, v);
             sample_point(L, v, comp, d, a.k, sx[t], sy[t], sz[t]);
@@ -130,12 +147,11 @@ __global__ __launch_bounds__(kWaveBlock) void k_flood_tiles(
             best[t] = u;
             M[t] = seed[j];
         }
-        live[t] = valid[t] && !(__fsqrt_rn(best[t]) < M[t]);
+        live[t] = valid && !(__fsqrt_rn(best[t]) < M[t]);
     }
-
+    const float h = g.h, eps = g.eps;
     // initial box: the cells of the live samples
     int lo[3] = {1 << 30, 1 << 30, 1 << 30}, hi[3] = {-1, -1, -1};
-    bool any = false;
 #pragma unroll
     for (int t = 0; t < T; ++t) {
         if (live[t]) {
@@ -145,93 +161,117 @@ __global__ __launch_bounds__(kWaveBlock) void k_flood_tiles(
             lo[0] = min(lo[0], cx); hi[0] = max(hi[0], cx);
             lo[1] = min(lo[1], cy); hi[1] = max(hi[1], cy);
             lo[2] = min(lo[2], cz); hi[2] = max(hi[2], cz);
-            any = true;
         }
     }
-    unsigned long long nev = 0;
-    if (__any(any)) {
 #pragma unroll
-        for (int ax = 0; ax < 3; ++ax) {
+    for (int ax = 0; ax < 3; ++ax) {
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            lo[ax] = min(lo[ax], __shfl_xor(lo[ax], o, 64));
+            hi[ax] = max(hi[ax], __shfl_xor(hi[ax], o, 64));
+        }
+        lo[ax] = __builtin_amdgcn_readfirstlane(lo[ax]);
+        hi[ax] = __builtin_amdgcn_readfirstlane(hi[ax]);
+    }
+    unsigned long long nev = 0;
+    const bool any_live = hi[0] >= 0;
+    const bool compact = any_live && hi[0] - lo[0] < a.max_extent && hi[1] - lo[1] < a.max_extent &&
+                         hi[2] - lo[2] < a.max_extent && a.radius_budget >= 0;
+    if (compact) {
+        int olo[3] = {lo[0], lo[1], lo[2]}, ohi[3] = {lo[0] - 1, lo[1] - 1, lo[2] - 1};  // empty old box
+        for (int r = 0;; ++r) {
+            // live-sample bounding box and largest bound: a coarse cull for the rows
+            float lx0 = INFINITY, lx1 = -INFINITY, ly0 = INFINITY, ly1 = -INFINITY, lz0 = INFINITY, lz1 = -INFINITY;
+            float bmax = 0.f;
+#pragma unroll
+            for (int t = 0; t < T; ++t)
+                if (live[t]) {
+                    lx0 = fminf(lx0, sx[t]); lx1 = fmaxf(lx1, sx[t]);
+                    ly0 = fminf(ly0, sy[t]); ly1 = fmaxf(ly1, sy[t]);
+                    lz0 = fminf(lz0, sz[t]); lz1 = fmaxf(lz1, sz[t]);
+                    bmax = fmaxf(bmax, best[t]);
+                }
 #pragma unroll
             for (int o = 32; o > 0; o >>= 1) {
-                lo[ax] = min(lo[ax], __shfl_xor(lo[ax], o, 64));
-                hi[ax] = max(hi[ax], __shfl_xor(hi[ax], o, 64));
+                lx0 = fminf(lx0, __shfl_xor(lx0, o, 64)); lx1 = fmaxf(lx1, __shfl_xor(lx1, o, 64));
+                ly0 = fminf(ly0, __shfl_xor(ly0, o, 64)); ly1 = fmaxf(ly1, __shfl_xor(ly1, o, 64));
+                lz0 = fminf(lz0, __shfl_xor(lz0, o, 64)); lz1 = fmaxf(lz1, __shfl_xor(lz1, o, 64));
+                bmax = fmaxf(bmax, __shfl_xor(bmax, o, 64));
             }
-            lo[ax] = __builtin_amdgcn_readfirstlane(lo[ax]);
-            hi[ax] = __builtin_amdgcn_readfirstlane(hi[ax]);
-        }
-        int olo[3] = {lo[0], lo[1], lo[2]}, ohi[3] = {lo[0] - 1, lo[1] - 1, lo[2] - 1};  // empty old box
-        bool first = true;
-        const float h = g.h, eps = g.eps;
-        while (true) {
-            // scan the rows of box [lo,hi] minus box [olo,ohi]
-            for (int z = lo[2]; z <= hi[2]; ++z) {
-                for (int y = lo[1]; y <= hi[1]; ++y) {
-                    const bool inner = !first && z >= olo[2] && z <= ohi[2] && y >= olo[1] && y <= ohi[1];
-                    for (int part = 0; part < 2; ++part) {
-                        int x0, x1;
-                        if (!inner) {
-                            if (part) break;
-                            x0 = lo[0];
-                            x1 = hi[0];
-                        } else if (part == 0) {
-                            x0 = lo[0];
-                            x1 = olo[0] - 1;
-                        } else {
-                            x0 = ohi[0] + 1;
-                            x1 = hi[0];
-                        }
-                        if (x0 > x1) continue;
+            // rows of box [lo,hi] minus box [olo,ohi], enumerated 64 at a time
+            const int nyb = hi[1] - lo[1] + 1;
+            const int nrows = nyb * (hi[2] - lo[2] + 1);
+            for (int base = 0; base < nrows; base += 64) {
+                const int i = base + lane;
+                const int y = lo[1] + i % nyb, z = lo[2] + i / nyb;
+                const bool inner = r > 0 && z >= olo[2] && z <= ohi[2] && y >= olo[1] && y <= ohi[1];
+#pragma unroll
+                for (int part = 0; part < 2; ++part) {
+                    int x0, x1;
+                    if (!inner) {
+                        x0 = lo[0];
+                        x1 = part ? lo[0] - 1 : hi[0];
+                    } else if (part == 0) {
+                        x0 = lo[0];
+                        x1 = olo[0] - 1;
+                    } else {
+                        x0 = ohi[0] + 1;
+                        x1 = hi[0];
+                    }
+                    bool ok = i < nrows && x0 <= x1;
+                    uint32_t p0 = 0, p1 = 0;
+                    if (ok) {
                         const int64_t c0 = g.cell_base + ((int64_t)z * g.ny + y) * g.nx + x0;
-                        const uint32_t p0 = __builtin_amdgcn_readfirstlane(cs[c0]);
-                        const uint32_t p1 = __builtin_amdgcn_readfirstlane(cs[c0 + (x1 - x0) + 1]);
-                        if (p0 == p1) continue;
-                        // conservative box of the run
-                        const float bx0 = g.ox + (float)x0 * h - eps, bx1 = g.ox + (float)(x1 + 1) * h + eps;
-                        const float by0 = g.oy + (float)y * h - eps, by1 = g.oy + (float)(y + 1) * h + eps;
-                        const float bz0 = g.oz + (float)z * h - eps, bz1 = g.oz + (float)(z + 1) * h + eps;
+                        p0 = cs[c0];
+                        p1 = cs[c0 + (x1 - x0) + 1];
+                        ok = p1 > p0;
+                    }
+                    if (ok) {
+                        // coarse: distance between the run's box and the live samples' box
+                        const float gx = fmaxf(fmaxf((g.ox + (float)x0 * h - eps) - lx1, lx0 - (g.ox + (float)(x1 + 1) * h + eps)), 0.f);
+                        const float gy = fmaxf(fmaxf((g.oy + (float)y * h - eps) - ly1, ly0 - (g.oy + (float)(y + 1) * h + eps)), 0.f);
+                        const float gz = fmaxf(fmaxf((g.oz + (float)z * h - eps) - lz1, lz0 - (g.oz + (float)(z + 1) * h + eps)), 0.f);
+                        ok = gx * gx + gy * gy + gz * gz < bmax;
+                    }
+                    uint64_t mask = __ballot(ok);
+                    while (mask) {
+                        const int src = __ffsll((unsigned long long)mask) - 1;
+                        mask &= mask - 1;
+                        const uint32_t q0 = __builtin_amdgcn_readlane(p0, src);
+                        const uint32_t q1 = __builtin_amdgcn_readlane(p1, src);
+                        const int rx0 = __builtin_amdgcn_readlane(x0, src);
+                        const int rx1 = __builtin_amdgcn_readlane(x1, src);
+                        const int ry = __builtin_amdgcn_readlane(y, src);
+                        const int rz = __builtin_amdgcn_readlane(z, src);
+                        const float bx0 = g.ox + (float)rx0 * h - eps, bx1 = g.ox + (float)(rx1 + 1) * h + eps;
+                        const float by0 = g.oy + (float)ry * h - eps, by1 = g.oy + (float)(ry + 1) * h + eps;
+                        const float bz0 = g.oz + (float)rz * h - eps, bz1 = g.oz + (float)(rz + 1) * h + eps;
                         bool need = false;
                         int nlive = 0;
 #pragma unroll
                         for (int t = 0; t < T; ++t) {
-                            if (live[t]) {
-                                const float ex = fmaxf(fmaxf(bx0 - sx[t], sx[t] - bx1), 0.f);
-                                const float ey = fmaxf(fmaxf(by0 - sy[t], sy[t] - by1), 0.f);
-                                const float ez = fmaxf(fmaxf(bz0 - sz[t], sz[t] - bz1), 0.f);
-                                const float lb = ex * ex + ey * ey + ez * ez;
-                                need |= lb < best[t];
-                            }
+                            if (live[t]) need |= box_lb2(sx[t], sy[t], sz[t], bx0, bx1, by0, by1, bz0, bz1) < best[t];
                             nlive += __popcll(__ballot(live[t]));
                         }
                         if (!__any(need)) continue;
-                        nev += (unsigned long long)(p1 - p0) * (unsigned long long)nlive;
-                        uint32_t p = p0;
-                        for (; p + 3 < p1; p += 4) {
-                            const float4 q0 = xs[p], q1 = xs[p + 1], q2 = xs[p + 2], q3 = xs[p + 3];
+                        nev += (unsigned long long)(q1 - q0) * (unsigned long long)nlive;
+                        uint32_t p = q0;
+                        for (; p + 3 < q1; p += 4) {
+                            const float4 c0 = xs[p], c1 = xs[p + 1], c2 = xs[p + 2], c3 = xs[p + 3];
 #pragma unroll
                             for (int t = 0; t < T; ++t) {
-                                const float d0 = dist2(sx[t], sy[t], sz[t], q0.x, q0.y, q0.z);
-                                const float d1 = dist2(sx[t], sy[t], sz[t], q1.x, q1.y, q1.z);
-                                const float d2 = dist2(sx[t], sy[t], sz[t], q2.x, q2.y, q2.z);
-                                const float d3 = dist2(sx[t], sy[t], sz[t], q3.x, q3.y, q3.z);
+                                const float d0 = dist2(sx[t], sy[t], sz[t], c0.x, c0.y, c0.z);
+                                const float d1 = dist2(sx[t], sy[t], sz[t], c1.x, c1.y, c1.z);
+                                const float d2 = dist2(sx[t], sy[t], sz[t], c2.x, c2.y, c2.z);
+                                const float d3 = dist2(sx[t], sy[t], sz[t], c3.x, c3.y, c3.z);
                                 best[t] = fminf(fminf(best[t], fminf(d0, d1)), fminf(d2, d3));
                             }
                         }
-                        for (; p + 1 < p1; p += 2) {
-                            const float4 q0 = xs[p];
-                            const float4 q1 = xs[p + 1];
-#pragma unroll
-                            for (int t = 0; t < T; ++t) {
-                                const float d0 = dist2(sx[t], sy[t], sz[t], q0.x, q0.y, q0.z);
-                                const float d1 = dist2(sx[t], sy[t], sz[t], q1.x, q1.y, q1.z);
-                                best[t] = fminf(best[t], fminf(d0, d1));
-                            }
-                        }
-                        if (p < p1) {
-                            const float4 q0 = xs[p];
+                        for (; p < q1; ++p) {
+                            const float4 c0 = xs[p];
 #pragma unroll
                             for (int t = 0; t < T; ++t)
-                                best[t] = fminf(best[t], dist2(sx[t], sy[t], sz[t], q0.x, q0.y, q0.z));
+                                best[t] = fminf(best[t], dist2(sx[t], sy[t], sz[t], c0.x, c0.y, c0.z));
                         }
                     }
                 }
@@ -253,22 +293,21 @@ __global__ __launch_bounds__(kWaveBlock) void k_flood_tiles(
                     if (hi[2] < g.nz - 1) ext = fminf(ext, (g.oz + (float)(hi[2] + 1) * h) - sz[t]);
                     ext -= eps;
                 }
-                const uint64_t kv = __hip_atomic_load(&key[sj[t]], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                M[t] = fmaxf(M[t], key_value(kv));
                 const bool complete = full || (ext > 0.f && best[t] <= ext * ext);
                 if (complete) {
-                    const float v = __fsqrt_rn(best[t]);
-                    if (v > seed[sj[t]]) {
-                        const uint64_t nk = ((uint64_t)__float_as_uint(v) << 32) | (uint64_t)(0xffffffffu - (uint32_t)sq[t]);
-                        atomicMax((unsigned long long *)&key[sj[t]], (unsigned long long)nk);
-                    }
+                    // exact minimum known; it matters only if it can beat the
+                    // seed (vertices always need their x*): hand it to phase B,
+                    // which finds x* inside the (tiny) ball of this radius
                     live[t] = false;
-                } else if (__fsqrt_rn(best[t]) < M[t]) {
-                    live[t] = false;
+                    cand[t] = d == 0 || __fsqrt_rn(best[t]) > seed[sj[t]];
+                } else {
+                    const uint64_t kv = __hip_atomic_load(&key[sj[t]], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    M[t] = fmaxf(M[t], key_value(kv));
+                    if (__fsqrt_rn(best[t]) < M[t]) live[t] = false;
                 }
                 anylive |= live[t];
             }
-            if (!__any(anylive) || full) break;
+            if (!__any(anylive) || full || r >= a.radius_budget) break;
             for (int ax = 0; ax < 3; ++ax) {
                 olo[ax] = lo[ax];
                 ohi[ax] = hi[ax];
@@ -276,110 +315,214 @@ __global__ __launch_bounds__(kWaveBlock) void k_flood_tiles(
             lo[0] = max(lo[0] - 1, 0); hi[0] = min(hi[0] + 1, g.nx - 1);
             lo[1] = max(lo[1] - 1, 0); hi[1] = min(hi[1] + 1, g.ny - 1);
             lo[2] = max(lo[2] - 1, 0); hi[2] = min(hi[2] + 1, g.nz - 1);
-            first = false;
+        }
+    }
+    // open samples (with their bound) and exact candidates go to phase B
+#pragma unroll
+    for (int t = 0; t < T; ++t) {
+        const bool push = live[t] || cand[t];
+        const uint64_t m = __ballot(push);
+        if (!m) continue;
+        uint32_t base = 0;
+        if (lane == 0) base = atomicAdd(hard_count, (uint32_t)__popcll(m));
+        base = __shfl(base, 0, 64);
+        if (push) {
+            const uint32_t slot = base + (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
+            const uint32_t g_id = (uint32_t)(sj[t] * (int64_t)a.n_int + sq[t]);
+            hard[slot] = ((uint64_t)g_id << 32) | __float_as_uint(best[t]);
         }
     }
     if (evals && lane == 0 && nev) atomicAdd(evals, nev);
+    if (stats && lane == 0 && nev) atomicAdd(&stats[4 * d + 2], nev);
 }
 
 // ---------------------------------------------------------------------------
-// winner record: one wave per simplex
+// phase B: one wavefront per open sample.  The lanes take the rows (y,z) of
+// the grid in Chebyshev rings around the sample's cell, 64 rows per round
+// trip; each lane scans the x-range of its row that can beat the current
+// bound and keeps the lexicographic minimum (d^2, point row); a wave
+// reduction after every chunk shares the bound.  Ring r cannot hold a point
+// closer than (r-1) h, which ends the search.
+
+struct DeepArgs {
+    int32_t d, k, n_int, B;
+};
+
+__device__ __forceinline__ void ring_pos(int i, int &r, int &dy, int &dz) {
+    // i-th row in ring order: ring r holds 8r rows (1 for r = 0) and starts
+    // at index (2r-1)^2
+    if (i == 0) {
+        r = 0; dy = 0; dz = 0;
+        return;
+    }
+    int rr = (int)((sqrtf((float)i + 0.5f) + 1.0f) * 0.5f);
+    while ((2 * rr - 1) * (2 * rr - 1) > i) --rr;
+    while ((2 * rr + 1) * (2 * rr + 1) <= i) ++rr;
+    r = rr;
+    const int p = i - (2 * rr - 1) * (2 * rr - 1);
+    const int side = p / (2 * rr), off = p % (2 * rr);
+    if (side == 0) { dy = -rr + off; dz = -rr; }
+    else if (side == 1) { dy = rr; dz = -rr + off; }
+    else if (side == 2) { dy = rr - off; dz = rr; }
+    else { dy = -rr; dz = rr - off; }
+}
+
+__device__ __forceinline__ void lex_min(float &bd, int32_t &bi, float od, int32_t oi) {
+    if (od < bd || (od == bd && oi < bi)) {
+        bd = od;
+        bi = oi;
+    }
+}
+
+__global__ __launch_bounds__(kWaveBlock) void k_flood_deep(
+    DeepArgs a, const float *__restrict__ L, const int32_t *__restrict__ simp, const int64_t *__restrict__ s_off,
+    const float *__restrict__ seed, uint64_t *__restrict__ key, const GridParam *__restrict__ gp,
+    const uint32_t *__restrict__ cs, const float4 *__restrict__ xs, const uint64_t *__restrict__ queue,
+    const uint32_t *__restrict__ queue_count, uint32_t *__restrict__ queue_next, int32_t *__restrict__ xstar,
+    unsigned long long *__restrict__ evals, unsigned long long *__restrict__ stats) {
+    const int lane = threadIdx.x & 63;
+    const uint32_t n = *queue_count;
+    if (stats && blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(&stats[4 * a.d + 1], (unsigned long long)n);
+    unsigned long long nev = 0;
+    while (true) {
+        uint32_t i = 0;
+        if (lane == 0) i = atomicAdd(queue_next, 1u);
+        i = __builtin_amdgcn_readfirstlane(i);
+        if (i >= n) break;
+        const uint64_t e = queue[i];
+        const uint32_t gid = (uint32_t)(e >> 32);
+        float bd = __uint_as_float((uint32_t)e);
+        int32_t bi = 0x7fffffff;
+        const int64_t j = gid / (uint32_t)a.n_int;
+        const int q = (int)(gid % (uint32_t)a.n_int);
+        int lo_b = 0, hi_b = a.B;
+        while (hi_b - lo_b > 1) {
+            int mid = (lo_b + hi_b) >> 1;
+            if (s_off[mid] <= j) lo_b = mid;
+            else hi_b = mid;
+        }
+        const GridParam g = gp[lo_b];
+        int comp[4];
+        if (a.d == 0) comp[0] = a.k;
+        else unrank_interior(q, a.d, a.k, comp);
+        int32_t v[4];
+        simplex_vertices(simp, a.d, j, v);
+        float sx, sy, sz;
+        sample_point(L, v, comp, a.d, a.k, sx, sy, sz);
+        const float sd = seed[j];
+        float M = fmaxf(sd, key_value(__hip_atomic_load(&key[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)));
+        bool retired = a.d > 0 && __fsqrt_rn(bd) < M;
+        const int cy = cell_of(sy, g.oy, g.inv_h, g.ny), cz = cell_of(sz, g.oz, g.inv_h, g.nz);
+        const int rmax = max(max(cy, g.ny - 1 - cy), max(cz, g.nz - 1 - cz));
+        const float h = g.h, eps = g.eps;
+        for (int base = 0; !retired; base += 64) {
+            int r0, dy0, dz0;
+            ring_pos(base, r0, dy0, dz0);
+            if (r0 > rmax) break;
+            const float lbr = fmaxf((float)(r0 - 1) * h - eps, 0.f);
+            if (lbr * lbr > bd) break;
+            int r, dy, dz;
+            ring_pos(base + lane, r, dy, dz);
+            const int y = cy + dy, z = cz + dz;
+            float lbd = bd;
+            int32_t lbi = bi;
+            if (r <= rmax && y >= 0 && y < g.ny && z >= 0 && z < g.nz) {
+                const float ez = fmaxf(fmaxf((g.oz + (float)z * h - eps) - sz, sz - (g.oz + (float)(z + 1) * h + eps)), 0.f);
+                const float ey = fmaxf(fmaxf((g.oy + (float)y * h - eps) - sy, sy - (g.oy + (float)(y + 1) * h + eps)), 0.f);
+                const float lzy = ez * ez + ey * ey;
+                if (!(lzy > bd)) {
+                    const float w = sqrtf(fmaxf(bd - lzy, 0.f)) + eps;
+                    const int x0 = cell_of(sx - w, g.ox, g.inv_h, g.nx);
+                    const int x1 = cell_of(sx + w, g.ox, g.inv_h, g.nx);
+                    const int64_t c0 = g.cell_base + ((int64_t)z * g.ny + y) * g.nx;
+                    const uint32_t p0 = cs[c0 + x0], p1 = cs[c0 + x1 + 1];
+                    nev += p1 - p0;
+                    uint32_t p = p0;
+                    for (; p + 1 < p1; p += 2) {
+                        const float4 c = xs[p], c2 = xs[p + 1];
+                        lex_min(lbd, lbi, dist2(sx, sy, sz, c.x, c.y, c.z), __float_as_int(c.w));
+                        lex_min(lbd, lbi, dist2(sx, sy, sz, c2.x, c2.y, c2.z), __float_as_int(c2.w));
+                    }
+                    if (p < p1) {
+                        const float4 c = xs[p];
+                        lex_min(lbd, lbi, dist2(sx, sy, sz, c.x, c.y, c.z), __float_as_int(c.w));
+                    }
+                }
+            }
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) {
+                const float od = __shfl_xor(lbd, o, 64);
+                const int32_t oi = __shfl_xor(lbi, o, 64);
+                lex_min(lbd, lbi, od, oi);
+            }
+            bd = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(lbd)));
+            bi = __builtin_amdgcn_readfirstlane(lbi);
+            if (a.d > 0) {
+                if ((base & 511) == 448)
+                    M = fmaxf(M, key_value(__hip_atomic_load(&key[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)));
+                retired = __fsqrt_rn(bd) < M;
+            }
+        }
+        if (!retired && lane == 0) {
+            const float vv = __fsqrt_rn(bd);
+            if (a.d == 0 || vv > sd) {
+                xstar[gid] = bi;
+                const uint64_t nk = ((uint64_t)__float_as_uint(vv) << 32) | (uint64_t)(0xffffffffu - (uint32_t)q);
+                atomicMax((unsigned long long *)&key[j], (unsigned long long)nk);
+            }
+        }
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) nev += __shfl_xor(nev, o, 64);
+    if (evals && lane == 0 && nev) atomicAdd(evals, nev);
+    if (stats && lane == 0 && nev) atomicAdd(&stats[4 * a.d + 3], nev);
+}
+
+// ---------------------------------------------------------------------------
+// winner record and final value: one thread per simplex.  An own sample won
+// if the key is set (x* was written by phase B); otherwise the value is the
+// seed and the winner is inherited from the first facet attaining it.
 
 __device__ __forceinline__ uint32_t pack_comp(const int a[4]) {
     return (uint32_t)a[0] | ((uint32_t)a[1] << 8) | ((uint32_t)a[2] << 16) | ((uint32_t)a[3] << 24);
 }
 
-__global__ __launch_bounds__(kWaveBlock) void k_winner(
-    int d, int k, int64_t n, const float *__restrict__ L, const int32_t *__restrict__ simp,
-    const int32_t *__restrict__ tri_edges, const int32_t *__restrict__ tet_tris, const int64_t *__restrict__ s_off,
-    int32_t B, const float *__restrict__ seed, const uint64_t *__restrict__ key, const GridParam *__restrict__ gp,
-    const uint32_t *__restrict__ cs, const float4 *__restrict__ xs, const float *__restrict__ fprev,
-    const int32_t *__restrict__ wxprev, const uint32_t *__restrict__ waprev, float *__restrict__ f,
-    int32_t *__restrict__ win_x, uint32_t *__restrict__ win_a) {
-    const int lane = threadIdx.x & 63;
-    const int64_t j = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+__global__ void k_winner(int d, int k, int64_t n, int n_int, const int32_t *__restrict__ simp,
+                         const int32_t *__restrict__ tri_edges, const int32_t *__restrict__ tet_tris,
+                         const float *__restrict__ seed, const uint64_t *__restrict__ key,
+                         const int32_t *__restrict__ xstar, const float *__restrict__ fprev,
+                         const int32_t *__restrict__ wxprev, const uint32_t *__restrict__ waprev,
+                         float *__restrict__ f, int32_t *__restrict__ win_x, uint32_t *__restrict__ win_a) {
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= n) return;
     const uint64_t kv = key[j];
-    const float sd = seed[j];
-    if (d > 0 && kv == 0) {
-        // the value comes from a facet: inherit its winner
-        if (lane == 0) {
-            int32_t fac[4];
-            for (int i = 0; i <= d; ++i) {
-                if (d == 1) fac[i] = simp[2 * j + (1 - i)];
-                else if (d == 2) fac[i] = tri_edges[3 * j + i];
-                else fac[i] = tet_tris[4 * j + i];
-            }
-            int fi = 0;
-            for (int i = 0; i <= d; ++i)
-                if (fprev[fac[i]] == sd) { fi = i; break; }
-            const uint32_t pa = waprev[fac[fi]];
-            int fa[4] = {(int)(pa & 255), (int)((pa >> 8) & 255), (int)((pa >> 16) & 255), (int)(pa >> 24)};
-            int aa[4] = {0, 0, 0, 0};
-            for (int i = 0, src = 0; i <= d; ++i) aa[i] = (i == fi) ? 0 : fa[src++];
-            f[j] = sd;
-            win_x[j] = wxprev[fac[fi]];
-            win_a[j] = pack_comp(aa);
-        }
+    if (kv != 0) {
+        const int q = (int)(0xffffffffu - (uint32_t)(kv & 0xffffffffu));
+        int comp[4] = {0, 0, 0, 0};
+        if (d == 0) comp[0] = k;
+        else unrank_interior(q, d, k, comp);
+        f[j] = key_value(kv);
+        win_x[j] = xstar[j * (int64_t)n_int + q];
+        win_a[j] = pack_comp(comp);
         return;
     }
-    // the simplex's own sample wins (vertices always search their own point)
-    int lo_b = 0, hi_b = B;
-    while (hi_b - lo_b > 1) {
-        int mid = (lo_b + hi_b) >> 1;
-        if (s_off[mid] <= j) lo_b = mid;
-        else hi_b = mid;
+    const float sd = seed[j];
+    int32_t fac[4];
+    for (int i = 0; i <= d; ++i) {
+        if (d == 1) fac[i] = simp[2 * j + (1 - i)];
+        else if (d == 2) fac[i] = tri_edges[3 * j + i];
+        else fac[i] = tet_tris[4 * j + i];
     }
-    const GridParam g = gp[lo_b];
-    int comp[4] = {0, 0, 0, 0};
-    float v = 0.f;
-    if (d == 0) {
-        comp[0] = k;
-        v = kv ? key_value(kv) : 0.f;
-    } else {
-        unrank_interior((int)(0xffffffffu - (uint32_t)(kv & 0xffffffffu)), d, k, comp);
-        v = key_value(kv);
-    }
-    int32_t vv[4];
-    simplex_vertices(simp, d, j, vv);
-    float sx, sy, sz;
-    sample_point(L, vv, comp, d, k, sx, sy, sz);
-    const float r = v * (1.0f + 1e-6f) + g.eps + 1e-30f;
-    const int x0 = cell_of(sx - r, g.ox, g.inv_h, g.nx), x1 = cell_of(sx + r, g.ox, g.inv_h, g.nx);
-    const int y0 = cell_of(sy - r, g.oy, g.inv_h, g.ny), y1 = cell_of(sy + r, g.oy, g.inv_h, g.ny);
-    const int z0 = cell_of(sz - r, g.oz, g.inv_h, g.nz), z1 = cell_of(sz + r, g.oz, g.inv_h, g.nz);
-    const int ny_ = y1 - y0 + 1;
-    const int nrow = ny_ * (z1 - z0 + 1);
-    float bd = INFINITY;
-    int32_t bi = 0x7fffffff;
-    for (int rr = lane; rr < nrow; rr += 64) {
-        const int z = z0 + rr / ny_, y = y0 + rr % ny_;
-        const int64_t c0 = g.cell_base + ((int64_t)z * g.ny + y) * g.nx + x0;
-        const uint32_t p0 = cs[c0], p1 = cs[c0 + (x1 - x0) + 1];
-        for (uint32_t p = p0; p < p1; ++p) {
-            const float4 q = xs[p];
-            const float dd = dist2(sx, sy, sz, q.x, q.y, q.z);
-            const int32_t qi = __float_as_int(q.w);
-            if (dd < bd || (dd == bd && qi < bi)) {
-                bd = dd;
-                bi = qi;
-            }
-        }
-    }
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-        const float od = __shfl_xor(bd, o, 64);
-        const int32_t oi = __shfl_xor(bi, o, 64);
-        if (od < bd || (od == bd && oi < bi)) {
-            bd = od;
-            bi = oi;
-        }
-    }
-    if (lane == 0) {
-        f[j] = d == 0 ? __fsqrt_rn(bd) : v;
-        win_x[j] = bi;
-        win_a[j] = pack_comp(comp);
-    }
+    int fi = 0;
+    for (int i = 0; i <= d; ++i)
+        if (fprev[fac[i]] == sd) { fi = i; break; }
+    const uint32_t pa = waprev[fac[fi]];
+    const int fa[4] = {(int)(pa & 255), (int)((pa >> 8) & 255), (int)((pa >> 16) & 255), (int)(pa >> 24)};
+    int aa[4] = {0, 0, 0, 0};
+    for (int i = 0, src = 0; i <= d; ++i) aa[i] = (i == fi) ? 0 : fa[src++];
+    f[j] = sd;
+    win_x[j] = wxprev[fac[fi]];
+    win_a[j] = pack_comp(aa);
 }
 
 // ---------------------------------------------------------------------------
@@ -395,8 +538,16 @@ size_t flood_workspace(const flood_problem *pb, float alpha, FloodSizes *sz) {
         n[d] = pb->s_off[d][pb->B];
         nmax = n[d] > nmax ? n[d] : nmax;
     }
+    int64_t smax = 0;
+    for (int d = 0; d < 4; ++d) {
+        int64_t sm = n[d] * n_interior(d, pb->k);
+        smax = sm > smax ? sm : smax;
+    }
     bytes += sizeof(float) * (nmax + 1) + 256;        // seed
     bytes += sizeof(uint64_t) * (nmax + 1) + 256;     // key
+    bytes += sizeof(uint64_t) * (smax + 1) + 256;     // open-sample queue
+    bytes += sizeof(int32_t) * (smax + 1) + 256;      // x* of candidate samples
+    bytes += sizeof(uint32_t) * 8 + 256;              // queue counters
     bytes += 4 * (sizeof(int64_t) * (pb->B + 1) + 256); // tile offsets
     bytes += 1024;
     if (sz) {
@@ -408,12 +559,13 @@ size_t flood_workspace(const flood_problem *pb, float alpha, FloodSizes *sz) {
 }
 
 template <int T>
-static void launch_tiles(const TileArgs &ta, int wpb, hipStream_t s, const float *L, const int32_t *lxidx,
-                         const int32_t *simp, const int64_t *s_off, const int64_t *tile_off, const float *seed,
-                         uint64_t *key, const GridWork &g, uint64_t *evals) {
+static void launch_tiles(const TileArgs &ta, int wpb, hipStream_t s, const float *L, const int32_t *simp,
+                         const int64_t *s_off, const int64_t *tile_off, const float *seed, uint64_t *key,
+                         const GridWork &g, uint64_t *hard, uint32_t *hard_count, uint64_t *evals, uint64_t *stats) {
     const int64_t nb = (ta.n_tiles + wpb - 1) / wpb;
-    hipLaunchKernelGGL(k_flood_tiles<T>, dim3((unsigned)nb), dim3(64 * wpb), 0, s, ta, L, lxidx, simp, s_off, tile_off,
-                       seed, key, g.gp, g.cell_start, g.xs, (unsigned long long *)evals);
+    hipLaunchKernelGGL(k_flood_tiles<T>, dim3((unsigned)nb), dim3(64 * wpb), 0, s, ta, L, simp, s_off, tile_off,
+                       seed, key, g.gp, g.cell_start, g.xs, hard, hard_count, (unsigned long long *)evals,
+                       (unsigned long long *)stats);
 }
 
 hipError_t flood_run(const flood_problem *pb, const flood_tuning &tu, const flood_outputs *out, void *ws,
@@ -425,8 +577,16 @@ hipError_t flood_run(const flood_problem *pb, const flood_tuning &tu, const floo
     grid_carve(c, pb->B, sz.total_pts, sz.total_cells, g);
     int64_t nmax = 0;
     for (int d = 0; d < 4; ++d) nmax = sz.n[d] > nmax ? sz.n[d] : nmax;
+    int64_t smax = 0;
+    for (int d = 0; d < 4; ++d) {
+        int64_t sm = sz.n[d] * n_interior(d, pb->k);
+        smax = sm > smax ? sm : smax;
+    }
     float *seed = c.take<float>(nmax + 1);
     uint64_t *key = c.take<uint64_t>(nmax + 1);
+    uint64_t *hard = c.take<uint64_t>(smax + 1);
+    int32_t *xstar = c.take<int32_t>(smax + 1);
+    uint32_t *counters = c.take<uint32_t>(8);
     int64_t *tile_off[4];
     for (int d = 0; d < 4; ++d) tile_off[d] = c.take<int64_t>(pb->B + 1);
     if (!c.ok()) return hipErrorOutOfMemory;
@@ -446,6 +606,8 @@ hipError_t flood_run(const flood_problem *pb, const flood_tuning &tu, const floo
                            pb->tri_edges, pb->tet_tris, d > 0 ? out->f[d - 1] : nullptr, seed);
         e = fill_u64(key, 0ull, n, s);
         if (e != hipSuccess) return e;
+        e = fill_u32(counters, 0u, 8, s);
+        if (e != hipSuccess) return e;
         if (nint > 0) {
             const int64_t tsamp = 64 * (int64_t)T;
             int64_t ntiles = 0;
@@ -458,26 +620,35 @@ hipError_t flood_run(const flood_problem *pb, const flood_tuning &tu, const floo
                 ta.n_int = (int32_t)nint;
                 ta.landmarks_in_x = pb->landmarks_in_x;
                 ta.B = pb->B;
+                ta.radius_budget = tu.tile_shells - 1;  // -2 disables the cooperative phase
+                ta.max_extent = 8;
                 ta.pad = 0;
                 ta.n_tiles = ntiles;
                 if (out->tile_events[2 * d]) {
                     e = hipEventRecord((hipEvent_t)out->tile_events[2 * d], s);
                     if (e != hipSuccess) return e;
                 }
-                if (T == 1) launch_tiles<1>(ta, wpb, s, pb->Lxyz, pb->l_xidx, simp, soff_d, tile_off[d], seed, key, g, out->evals);
-                else if (T == 2) launch_tiles<2>(ta, wpb, s, pb->Lxyz, pb->l_xidx, simp, soff_d, tile_off[d], seed, key, g, out->evals);
-                else launch_tiles<4>(ta, wpb, s, pb->Lxyz, pb->l_xidx, simp, soff_d, tile_off[d], seed, key, g, out->evals);
+                if (T == 1) launch_tiles<1>(ta, wpb, s, pb->Lxyz, simp, soff_d, tile_off[d], seed, key, g, hard, counters, out->evals, out->stats);
+                else if (T == 2) launch_tiles<2>(ta, wpb, s, pb->Lxyz, simp, soff_d, tile_off[d], seed, key, g, hard, counters, out->evals, out->stats);
+                else launch_tiles<4>(ta, wpb, s, pb->Lxyz, simp, soff_d, tile_off[d], seed, key, g, hard, counters, out->evals, out->stats);
+                DeepArgs da;
+                da.d = d;
+                da.k = pb->k;
+                da.n_int = (int32_t)nint;
+                da.B = pb->B;
+                hipLaunchKernelGGL(k_flood_deep, dim3(2048), dim3(256), 0, s, da, pb->Lxyz, simp, soff_d, seed, key,
+                                   g.gp, g.cell_start, g.xs, hard, counters, counters + 1, xstar,
+                                   (unsigned long long *)out->evals, (unsigned long long *)out->stats);
                 if (out->tile_events[2 * d + 1]) {
                     e = hipEventRecord((hipEvent_t)out->tile_events[2 * d + 1], s);
                     if (e != hipSuccess) return e;
                 }
             }
         }
-        const int64_t wblocks = (n + 3) / 4;
-        hipLaunchKernelGGL(k_winner, dim3((unsigned)wblocks), dim3(256), 0, s, d, pb->k, n, pb->Lxyz, simp,
-                           pb->tri_edges, pb->tet_tris, soff_d, pb->B, seed, key, g.gp, g.cell_start, g.xs,
-                           d > 0 ? out->f[d - 1] : nullptr, d > 0 ? out->win_x[d - 1] : nullptr,
-                           d > 0 ? out->win_a[d - 1] : nullptr, out->f[d], out->win_x[d], out->win_a[d]);
+        hipLaunchKernelGGL(k_winner, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, d, pb->k, n, (int)nint,
+                           simp, pb->tri_edges, pb->tet_tris, seed, key, xstar, d > 0 ? out->f[d - 1] : nullptr,
+                           d > 0 ? out->win_x[d - 1] : nullptr, d > 0 ? out->win_a[d - 1] : nullptr, out->f[d],
+                           out->win_x[d], out->win_a[d]);
         e = hipGetLastError();
         if (e != hipSuccess) return e;
     }

@@ -186,18 +186,32 @@ __global__ __launch_bounds__(kBlock) void k_bbox(const float *X, const int64_t *
             mx[a] = fmaxf(mx[a], __shfl_xor(mx[a], o, 64));
         }
     }
-    if ((threadIdx.x & 63) == 0 && lo < hi) {
+    __shared__ float s_mn[3][kBlock / 64], s_mx[3][kBlock / 64];
+    const int wid = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0)
         for (int a = 0; a < 3; ++a) {
-            if (mn[a] <= mx[a]) {
-                atomicMin(&bbox[6 * b + a], float_key(mn[a]));
-                atomicMax(&bbox[6 * b + 3 + a], float_key(mx[a]));
+            s_mn[a][wid] = mn[a];
+            s_mx[a][wid] = mx[a];
+        }
+    __syncthreads();
+    if (threadIdx.x == 0 && lo < hi) {
+        for (int a = 0; a < 3; ++a) {
+            float m0 = s_mn[a][0], m1 = s_mx[a][0];
+            for (int w = 1; w < kBlock / 64; ++w) {
+                m0 = fminf(m0, s_mn[a][w]);
+                m1 = fmaxf(m1, s_mx[a][w]);
+            }
+            if (m0 <= m1) {
+                atomicMin(&bbox[6 * b + a], float_key(m0));
+                atomicMax(&bbox[6 * b + 3 + a], float_key(m1));
             }
         }
     }
 }
 
 // one thread: grid parameters of every cloud (sequential prefix of the cell bases)
-__global__ void k_grid_params(const uint32_t *bbox, const int64_t *x_off, int32_t B, float alpha, GridParam *gp) {
+__global__ void k_grid_params(const uint32_t *bbox, const int64_t *x_off, int32_t B, float alpha, int32_t max_dim,
+                              GridParam *gp) {
     if (blockIdx.x != 0 || threadIdx.x != 0) return;
     int64_t base = 0;
     for (int32_t b = 0; b < B; ++b) {
@@ -225,7 +239,7 @@ __global__ void k_grid_params(const uint32_t *bbox, const int64_t *x_off, int32_
             nx = (int64_t)floor((double)e[0] / h) + 1;
             ny = (int64_t)floor((double)e[1] / h) + 1;
             nz = (int64_t)floor((double)e[2] / h) + 1;
-            if (nx <= (1 << 20) && ny <= (1 << 20) && nz <= (1 << 20) && nx * ny * nz <= cap) break;
+            if (nx <= max_dim && ny <= max_dim && nz <= max_dim && nx * ny * nz <= cap) break;
             h *= 1.05;
         }
         g.ox = lo[0]; g.oy = lo[1]; g.oz = lo[2];
@@ -243,20 +257,15 @@ __global__ void k_grid_params(const uint32_t *bbox, const int64_t *x_off, int32_
     }
 }
 
-__device__ inline int cell_coord(float v, float o, float inv_h, int n) {
-    float t = (v - o) * inv_h;
-    int c = (t >= 0.f) ? (int)t : 0;   // also maps NaN to 0
-    return c < n ? c : n - 1;
-}
 
 __global__ __launch_bounds__(kBlock) void k_count(const float *X, const GridParam *gp, uint32_t *pcell, uint32_t *counts) {
     const int b = blockIdx.y;
     const GridParam g = gp[b];
     const int64_t lo = g.pt_base, hi = g.pt_base + g.npts;
     for (int64_t i = lo + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < hi; i += (int64_t)gridDim.x * blockDim.x) {
-        int cx = cell_coord(X[3 * i], g.ox, g.inv_h, g.nx);
-        int cy = cell_coord(X[3 * i + 1], g.oy, g.inv_h, g.ny);
-        int cz = cell_coord(X[3 * i + 2], g.oz, g.inv_h, g.nz);
+        int cx = bin_coord(X[3 * i], g.ox, g.inv_h, g.nx);
+        int cy = bin_coord(X[3 * i + 1], g.oy, g.inv_h, g.ny);
+        int cz = bin_coord(X[3 * i + 2], g.oz, g.inv_h, g.nz);
         uint32_t c = (uint32_t)(g.cell_base + ((int64_t)cz * g.ny + cy) * g.nx + cx);
         pcell[i] = c;
         atomicAdd(&counts[c], 1u);
@@ -280,7 +289,7 @@ __global__ __launch_bounds__(kBlock) void k_scatter(const float *X, const GridPa
 }
 
 hipError_t grid_build(const float *X, int32_t B, const int64_t *x_off, const int64_t *x_off_d,
-                      float alpha, GridWork &g, hipStream_t s) {
+                      float alpha, GridWork &g, hipStream_t s, int32_t max_dim) {
     int64_t nmax = 0;
     for (int32_t b = 0; b < B; ++b) nmax = nmax > x_off[b + 1] - x_off[b] ? nmax : x_off[b + 1] - x_off[b];
     int bx = (int)((nmax + kBlock * 8 - 1) / (kBlock * 8));
@@ -288,7 +297,7 @@ hipError_t grid_build(const float *X, int32_t B, const int64_t *x_off, const int
     if (bx > 4096) bx = 4096;
     hipLaunchKernelGGL(k_bbox_init, dim3((6 * B + 255) / 256), dim3(256), 0, s, g.bbox, B);
     hipLaunchKernelGGL(k_bbox, dim3(bx, B), dim3(kBlock), 0, s, X, x_off_d, g.bbox);
-    hipLaunchKernelGGL(k_grid_params, dim3(1), dim3(1), 0, s, g.bbox, x_off_d, B, alpha, g.gp);
+    hipLaunchKernelGGL(k_grid_params, dim3(1), dim3(1), 0, s, g.bbox, x_off_d, B, alpha, max_dim, g.gp);
     hipError_t e = fill_u32(g.cell_start, 0u, g.total_cells + 1, s);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_count, dim3(bx, B), dim3(kBlock), 0, s, X, g.gp, g.pcell, g.cell_start);

@@ -53,6 +53,13 @@ __device__ inline float key_float(uint32_t k) {
     return __uint_as_float(u);
 }
 
+// cell coordinate of a coordinate value (the binning rule; NaN maps to 0)
+__device__ inline int bin_coord(float v, float o, float inv_h, int n) {
+    float t = (v - o) * inv_h;
+    int c = (t >= 0.f) ? (int)t : 0;
+    return c < n ? c : n - 1;
+}
+
 // ---- grid build (grid.hip) ----
 struct GridWork {
     GridParam *gp;        // [B]
@@ -68,7 +75,7 @@ struct GridWork {
 size_t grid_workspace(int32_t B, const int64_t *x_off, float alpha, int64_t *total_cells);
 void grid_carve(Carve &c, int32_t B, int64_t total_pts, int64_t total_cells, GridWork &g);
 hipError_t grid_build(const float *X, int32_t B, const int64_t *x_off, const int64_t *x_off_d,
-                      float alpha, GridWork &g, hipStream_t s);
+                      float alpha, GridWork &g, hipStream_t s, int32_t max_dim = 1 << 20);
 
 // generic helpers (grid.hip)
 hipError_t fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s);

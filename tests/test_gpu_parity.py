@@ -100,9 +100,11 @@ def test_tuning_invariance_and_determinism():
         assert np.array_equal(base["out"]["f"][d], again["out"]["f"][d])
         assert np.array_equal(base["out"]["win_x"][d], again["out"]["win_x"][d])
         assert np.array_equal(base["out"]["win_a"][d], again["out"]["win_a"][d])
-    assert base["out"]["evals"] == again["out"]["evals"]
+    # the number of evaluations may differ: the running max M that retires
+    # samples is read while other tiles are still raising it
     for tu in ({"samples_per_lane": 2}, {"samples_per_lane": 4}, {"cells_per_point": 0.2},
-               {"cells_per_point": 6.0, "waves_per_block": 1}):
+               {"cells_per_point": 6.0, "waves_per_block": 1}, {"tile_shells": -1}, {"tile_shells": 1},
+            {"tile_shells": 4, "samples_per_lane": 2}):
         other = run_single(X, 400, 6, tuning=tu)
         for d in range(4):
             assert np.array_equal(base["out"]["f"][d], other["out"]["f"][d]), (tu, d)
