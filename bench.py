@@ -118,8 +118,8 @@ def main():
     tuning = json.loads(args.tuning) if args.tuning else None
     pb = P.problem_from_complexes(Xd, [0, len(X)], Ld, [0, len(Lxyz)], [cx], args.k, l_xidx=idx.clone())
     run = P.api.FloodRun(pb, tuning, count_evals=True)
-    hev = HipEvents(8)
-    for i in range(8):
+    hev = HipEvents(12)
+    for i in range(12):
         run.out.tile_events[i] = hev.ev[i].value
     s0, s1, s2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
 
@@ -133,7 +133,7 @@ def main():
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
-    fps_ms, flood_ms, tile_ms, step_ms = [], [], [], []
+    fps_ms, flood_ms, tile_ms, step_ms, stats_steps = [], [], [], [], []
     evals = []
     t_start = torch.cuda.Event(enable_timing=True)
     t_end = torch.cuda.Event(enable_timing=True)
@@ -147,16 +147,23 @@ def main():
         fps_ms.append(s0.elapsed_time(s1))
         flood_ms.append(s1.elapsed_time(s2))
         step_ms.append(s0.elapsed_time(s2))
-        tile_ms.append([hev.elapsed_ms(2 * d, 2 * d + 1) if (d == 0 or pb.n(d)) and P.n_interior(d, args.k) > 0 else 0.0
-                        for d in range(4)])
+        tile_ms.append([(hev.elapsed_ms(3 * d, 3 * d + 1), hev.elapsed_ms(3 * d + 1, 3 * d + 2))
+                        if (d == 0 or pb.n(d)) and P.n_interior(d, args.k) > 0 else (0.0, 0.0) for d in range(4)])
+        stats_steps.append(run.stats.view(4, 4).cpu().numpy().copy())
         evals.append(int(run.evals.item()))
     t_end.record()
     torch.cuda.synchronize()
     total_ms = t_start.elapsed_time(t_end)
     ms = total_ms / args.steps
     ev = int(np.median(evals))
-    tile_tot = float(np.mean([sum(t) for t in tile_ms]))
-    achieved = FLOP_PER_EVAL * ev / (tile_tot * 1e-3) / 1e12
+    # per phase: cooperative tile search (k_flood_tiles) and per-sample search
+    # (k_flood_deep), each summed over the four dimensions
+    a_ms = float(np.mean([sum(t[d][0] for d in range(4)) for t in tile_ms]))
+    b_ms = float(np.mean([sum(t[d][1] for d in range(4)) for t in tile_ms]))
+    st = np.mean(stats_steps, axis=0)
+    a_ev, b_ev = float(st[:, 2].sum()), float(st[:, 3].sum())
+    dominant = ("k_flood_deep", b_ev, b_ms) if b_ms >= a_ms else ("k_flood_tiles", a_ev, a_ms)
+    achieved = FLOP_PER_EVAL * dominant[1] / (dominant[2] * 1e-3) / 1e12
     nsimp = V + E + F + T
     out = {
         "metric": METRIC,
@@ -181,11 +188,14 @@ def main():
                                  "tile_evals": [int(v) for v in run.stats.view(4, 4)[:, 2].cpu()],
                                  "per_sample_evals": [int(v) for v in run.stats.view(4, 4)[:, 3].cpu()]},
         "stage_ms": {"fps": float(np.mean(fps_ms)), "filtration": float(np.mean(flood_ms)),
-                     "flood_search_per_dim": [float(np.mean([t[d] for t in tile_ms])) for d in range(4)],
+                     "tile_search_per_dim": [float(np.mean([t[d][0] for t in tile_ms])) for d in range(4)],
+                     "per_sample_search_per_dim": [float(np.mean([t[d][1] for t in tile_ms])) for d in range(4)],
                      "delaunay_host_once": del_ms},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / FP32_PEAK_TFLOPS, "traffic": None,
-                     "kernel": "k_flood_tiles", "flop_per_eval": FLOP_PER_EVAL},
+                     "kernel": dominant[0], "kernel_ms_per_step": dominant[2], "flop_per_eval": FLOP_PER_EVAL,
+                     "other_search_kernel": {"k_flood_tiles": {"ms": a_ms, "evals": a_ev},
+                                             "k_flood_deep": {"ms": b_ms, "evals": b_ev}}},
     }
     if not args.no_cpu_baseline:
         print("bench: cpu baseline (oracle) ...", file=sys.stderr, flush=True)

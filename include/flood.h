@@ -155,9 +155,10 @@ typedef struct {
  * ties, and the first attaining facet when the value comes from a face).
  * evals: device uint64 [1] or NULL; receives (+=) the number of sample-point
  * distance evaluations executed for live samples.
- * tile_events: optional caller-created hipEvent_t handles; entries 2d and
- * 2d+1 are recorded on `stream` right before and after the flooding-search
- * kernels of dimension d (NULL entries are skipped).  For profiling only.
+ * tile_events: optional caller-created hipEvent_t handles; entries 3d,
+ * 3d+1 and 3d+2 are recorded on `stream` before the cooperative tile search
+ * of dimension d, between it and the per-sample search, and after the
+ * per-sample search (NULL entries are skipped).  For profiling only.
  * stats: device uint64 [16] or NULL; receives (+=), for dimension d,
  * [4d+1] samples handed to the per-sample search, [4d+2] evaluations in the
  * cooperative tile search, [4d+3] evaluations in the per-sample search. */
@@ -166,7 +167,7 @@ typedef struct {
     int32_t *win_x[4];
     uint32_t *win_a[4];
     uint64_t *evals;
-    void *tile_events[8];
+    void *tile_events[12];
     uint64_t *stats;
 } flood_outputs;
 
@@ -175,12 +176,15 @@ typedef struct {
  * uniform-grid cells per point, 0.05..64), samples_per_lane (1, 2 or 4),
  * waves_per_block (1..16), tile_shells (cell shells a wave scans
  * cooperatively around its samples before handing open samples to the
- * per-lane search, 1..8; -1 sends every sample to the per-lane search). */
+ * per-sample search, 1..8; -1 sends every sample to the per-sample search),
+ * tile_extent (a tile whose samples span more cells than this along an axis
+ * skips the cooperative search, 2..64). */
 typedef struct {
     float cells_per_point;
     int32_t samples_per_lane;
     int32_t waves_per_block;
     int32_t tile_shells;
+    int32_t tile_extent;
 } flood_tuning;
 
 size_t flood_filtration_workspace_size(const flood_problem *pb, const flood_tuning *tune);

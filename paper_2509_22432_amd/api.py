@@ -219,6 +219,7 @@ def _tuning(tuning):
     t.samples_per_lane = int(tuning.get("samples_per_lane", 0))
     t.waves_per_block = int(tuning.get("waves_per_block", 0))
     t.tile_shells = int(tuning.get("tile_shells", 0))
+    t.tile_extent = int(tuning.get("tile_extent", 0))
     return t
 
 

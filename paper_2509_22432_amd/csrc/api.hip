@@ -3,7 +3,7 @@
 #include <cmath>
 #include <string>
 
-#include "internal.hpp"
+#include "sample.hpp"
 
 namespace flood_host {
 static thread_local std::string g_err;
@@ -42,11 +42,13 @@ flood_tuning default_tuning(const flood_tuning *t) {
     r.samples_per_lane = 1;
     r.waves_per_block = 4;
     r.tile_shells = 2;
+    r.tile_extent = 16;
     if (t) {
         if (t->cells_per_point != 0) r.cells_per_point = t->cells_per_point;
         if (t->samples_per_lane != 0) r.samples_per_lane = t->samples_per_lane;
         if (t->waves_per_block != 0) r.waves_per_block = t->waves_per_block;
         if (t->tile_shells != 0) r.tile_shells = t->tile_shells;
+        if (t->tile_extent != 0) r.tile_extent = t->tile_extent;
     }
     return r;
 }
@@ -59,6 +61,7 @@ flood_status check_tuning(const flood_tuning &t) {
     if (t.waves_per_block < 1 || t.waves_per_block > 16) return fail(FLOOD_EINVAL, "tuning: waves_per_block outside [1, 16]");
     if (t.tile_shells < -1 || t.tile_shells > 8 || t.tile_shells == 0)
         return fail(FLOOD_EINVAL, "tuning: tile_shells must be -1 or in [1, 8]");
+    if (t.tile_extent < 2 || t.tile_extent > 64) return fail(FLOOD_EINVAL, "tuning: tile_extent outside [2, 64]");
     return FLOOD_OK;
 }
 
@@ -78,6 +81,15 @@ flood_status check_problem(const flood_problem *pb) {
         if (pb->s_off[d][pb->B] > 0 && (!pb->simp[d] || !pb->s_off_d[d]))
             return fail(FLOOD_EINVAL, "problem: NULL simplex array");
         if (pb->s_off[d][pb->B] >= kMaxPoints) return fail(FLOOD_EUNSUPPORTED, "problem: too many simplices");
+    }
+    for (int d = 0; d < 4; ++d) {
+        const int64_t *so = d == 0 ? pb->l_off : pb->s_off[d];
+        const int64_t nint = flood::n_interior(d, pb->k);
+        if (so[pb->B] * nint >= ((int64_t)1 << 31))
+            return fail(FLOOD_EUNSUPPORTED, "problem: more than 2^31 - 1 interior samples in one dimension");
+        int64_t bk = 0;
+        for (int32_t b = 0; b < pb->B; ++b) bk += (int64_t)1 << (3 * flood::morton_bits((so[b + 1] - so[b]) * nint));
+        if (bk >= ((int64_t)1 << 32) - 1) return fail(FLOOD_EUNSUPPORTED, "problem: too many clouds for the sample sort");
     }
     if (pb->s_off[2][pb->B] > 0 && !pb->tri_edges) return fail(FLOOD_EINVAL, "problem: tri_edges is NULL");
     if (pb->s_off[3][pb->B] > 0 && !pb->tet_tris) return fail(FLOOD_EINVAL, "problem: tet_tris is NULL");

@@ -27,6 +27,7 @@
 namespace flood {
 
 static constexpr int kWaveBlock = 256;
+static constexpr int kU = 8;  // points per lane per step in the per-sample search
 
 // ---------------------------------------------------------------------------
 // per-dimension helpers
@@ -63,6 +64,66 @@ __global__ void k_seed(int d, int64_t n, const int32_t *__restrict__ simp1, cons
 __device__ __forceinline__ float key_value(uint64_t kv) { return __uint_as_float((uint32_t)(kv >> 32)); }
 
 // ---------------------------------------------------------------------------
+// sample order: a counting sort of each dimension's interior samples by the
+// Morton code of their position on a per-cloud 2^m cube (m chosen for about
+// four samples per bucket), so that 64 consecutive samples form a compact
+// tile whatever simplices they come from.
+
+__global__ void k_bucket_base(const int64_t *s_off, int32_t B, int64_t n_int, int32_t *mbits, uint32_t *bbase) {
+    if (blockIdx.x != 0 || threadIdx.x != 0) return;
+    uint32_t base = 0;
+    for (int32_t b = 0; b < B; ++b) {
+        const int m = morton_bits((s_off[b + 1] - s_off[b]) * n_int);
+        mbits[b] = m;
+        bbase[b] = base;
+        base += 1u << (3 * m);
+    }
+    bbase[B] = base;
+}
+
+__global__ void k_sample_keys(int d, int k, int n_int, int32_t B, int64_t S, const float *__restrict__ L,
+                              const int32_t *__restrict__ simp, const int64_t *__restrict__ s_off,
+                              const GridParam *__restrict__ gp, const int32_t *__restrict__ mbits,
+                              const uint32_t *__restrict__ bbase, uint32_t *__restrict__ skey,
+                              uint32_t *__restrict__ counts) {
+    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (gid >= S) return;
+    const int64_t j = gid / n_int;
+    const int q = (int)(gid % n_int);
+    int lo_b = 0, hi_b = B;
+    while (hi_b - lo_b > 1) {
+        const int mid = (lo_b + hi_b) >> 1;
+        if (s_off[mid] <= j) lo_b = mid;
+        else hi_b = mid;
+    }
+    const GridParam g = gp[lo_b];
+    int comp[4];
+    if (d == 0) comp[0] = k;
+    else unrank_interior(q, d, k, comp);
+    int32_t v[4];
+    simplex_vertices(simp, d, j, v);
+    float sx, sy, sz;
+    sample_point(L, v, comp, d, k, sx, sy, sz);
+    const int m = mbits[lo_b];
+    const float ext = (float)max(max(g.nx, g.ny), g.nz) * g.h;
+    const float sc = (float)(1 << m) / ext;
+    const int top = (1 << m) - 1;
+    const int qx = min(max((int)((sx - g.ox) * sc), 0), top);
+    const int qy = min(max((int)((sy - g.oy) * sc), 0), top);
+    const int qz = min(max((int)((sz - g.oz) * sc), 0), top);
+    const uint32_t key = bbase[lo_b] + (spread3(qx) | (spread3(qy) << 1) | (spread3(qz) << 2));
+    skey[gid] = key;
+    atomicAdd(&counts[key], 1u);
+}
+
+__global__ void k_sample_scatter(int64_t S, const uint32_t *__restrict__ skey, uint32_t *__restrict__ cursor,
+                                 uint32_t *__restrict__ order) {
+    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (gid >= S) return;
+    order[atomicAdd(&cursor[skey[gid]], 1u)] = (uint32_t)gid;
+}
+
+// ---------------------------------------------------------------------------
 // phase A: cooperative tile scan (compact tiles, bounded radius)
 
 struct TileArgs {
@@ -73,6 +134,9 @@ struct TileArgs {
     int64_t n_tiles;
 };
 
+// 0 in every lane, opaque to the compiler's uniformity analysis
+__device__ __forceinline__ uint32_t opaque_zero() { return __builtin_amdgcn_mbcnt_lo(0u, 0u); }
+
 __device__ __forceinline__ float box_lb2(float sx, float sy, float sz, float bx0, float bx1, float by0, float by1,
                                          float bz0, float bz1) {
     const float ex = fmaxf(fmaxf(bx0 - sx, sx - bx1), 0.f);
@@ -81,9 +145,10 @@ __device__ __forceinline__ float box_lb2(float sx, float sy, float sz, float bx0
     return ex * ex + ey * ey + ez * ez;
 }
 
-__device__ __forceinline__ void publish(uint64_t *key, const float *seed, int32_t j, int32_t q, float best) {
-    const float v = __fsqrt_rn(best);
-    if (v > seed[j]) {
+__device__ __forceinline__ void publish(uint64_t *key, const float *seed, int32_t j, int32_t q, float best,
+                                        bool always) {
+    const float v = sqrt_rn(best);
+    if (always || v > seed[j]) {
         const uint64_t nk = ((uint64_t)__float_as_uint(v) << 32) | (uint64_t)(0xffffffffu - (uint32_t)q);
         atomicMax((unsigned long long *)&key[j], (unsigned long long)nk);
     }
@@ -94,8 +159,8 @@ __global__ __launch_bounds__(kWaveBlock) void k_flood_tiles(
     TileArgs a, const float *__restrict__ L, const int32_t *__restrict__ simp, const int64_t *__restrict__ s_off,
     const int64_t *__restrict__ tile_off, const float *__restrict__ seed, uint64_t *__restrict__ key,
     const GridParam *__restrict__ gp, const uint32_t *__restrict__ cs, const float4 *__restrict__ xs,
-    uint64_t *__restrict__ hard, uint32_t *__restrict__ hard_count, unsigned long long *__restrict__ evals,
-    unsigned long long *__restrict__ stats) {
+    const uint32_t *__restrict__ order, uint64_t *__restrict__ hard, uint32_t *__restrict__ hard_count,
+    unsigned long long *__restrict__ evals, unsigned long long *__restrict__ stats) {
     const int lane = threadIdx.x & 63;
     const int wpb = blockDim.x >> 6;
     // wave-uniform by construction; readfirstlane lets the compiler keep the
@@ -117,20 +182,20 @@ __global__ __launch_bounds__(kWaveBlock) void k_flood_tiles(
 
     float sx[T], sy[T], sz[T], best[T], M[T];
     int32_t sj[T], sq[T];
-    bool live[T], cand[T];
+    bool live[T];
 #pragma unroll
     for (int t = 0; t < T; ++t) {
         const int64_t ls = ls0 + (int64_t)t * 64 + lane;
         const bool valid = ls < S;
-        cand[t] = false;
         sx[t] = sy[t] = sz[t] = 0.f;
         best[t] = 0.f;
         M[t] = 0.f;
         sj[t] = 0;
         sq[t] = 0;
         if (valid) {
-            const int64_t j = sbase + ls / a.n_int;
-            const int q = (int)(ls % a.n_int);
+            const uint32_t gid = order[sbase * a.n_int + ls];
+            const int64_t j = gid / (uint32_t)a.n_int;
+            const int q = (int)(gid % (uint32_t)a.n_int);
             sj[t] = (int32_t)j;
             sq[t] = q;
             int comp[4];
@@ -147,7 +212,7 @@ __global__ __launch_bounds__(kWaveBlock) void k_flood_tiles(
             best[t] = u;
             M[t] = seed[j];
         }
-        live[t] = valid && !(__fsqrt_rn(best[t]) < M[t]);
+        live[t] = valid && !(sqrt_rn(best[t]) < M[t]);
     }
     const float h = g.h, eps = g.eps;
     // initial box: the cells of the live samples
@@ -255,9 +320,13 @@ __global__ __launch_bounds__(kWaveBlock) void k_flood_tiles(
                         }
                         if (!__any(need)) continue;
                         nev += (unsigned long long)(q1 - q0) * (unsigned long long)nlive;
+                        // wave-uniform addresses, but issued as vector loads:
+                        // the scalar data cache is not kept coherent with the
+                        // scatter that rewrote xs earlier in this call
+                        const float4 *xv = xs + opaque_zero();
                         uint32_t p = q0;
                         for (; p + 3 < q1; p += 4) {
-                            const float4 c0 = xs[p], c1 = xs[p + 1], c2 = xs[p + 2], c3 = xs[p + 3];
+                            const float4 c0 = xv[p], c1 = xv[p + 1], c2 = xv[p + 2], c3 = xv[p + 3];
 #pragma unroll
                             for (int t = 0; t < T; ++t) {
                                 const float d0 = dist2(sx[t], sy[t], sz[t], c0.x, c0.y, c0.z);
@@ -268,7 +337,7 @@ __global__ __launch_bounds__(kWaveBlock) void k_flood_tiles(
                             }
                         }
                         for (; p < q1; ++p) {
-                            const float4 c0 = xs[p];
+                            const float4 c0 = xv[p];
 #pragma unroll
                             for (int t = 0; t < T; ++t)
                                 best[t] = fminf(best[t], dist2(sx[t], sy[t], sz[t], c0.x, c0.y, c0.z));
@@ -295,15 +364,14 @@ __global__ __launch_bounds__(kWaveBlock) void k_flood_tiles(
                 }
                 const bool complete = full || (ext > 0.f && best[t] <= ext * ext);
                 if (complete) {
-                    // exact minimum known; it matters only if it can beat the
-                    // seed (vertices always need their x*): hand it to phase B,
-                    // which finds x* inside the (tiny) ball of this radius
+                    // exact minimum: publish (value, rank); x* is found later
+                    // for the winning sample only
                     live[t] = false;
-                    cand[t] = d == 0 || __fsqrt_rn(best[t]) > seed[sj[t]];
+                    publish(key, seed, sj[t], sq[t], best[t], d == 0);
                 } else {
                     const uint64_t kv = __hip_atomic_load(&key[sj[t]], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                     M[t] = fmaxf(M[t], key_value(kv));
-                    if (__fsqrt_rn(best[t]) < M[t]) live[t] = false;
+                    if (sqrt_rn(best[t]) < M[t]) live[t] = false;
                 }
                 anylive |= live[t];
             }
@@ -317,10 +385,10 @@ __global__ __launch_bounds__(kWaveBlock) void k_flood_tiles(
             lo[2] = max(lo[2] - 1, 0); hi[2] = min(hi[2] + 1, g.nz - 1);
         }
     }
-    // open samples (with their bound) and exact candidates go to phase B
+    // open samples go to phase B with their bound
 #pragma unroll
     for (int t = 0; t < T; ++t) {
-        const bool push = live[t] || cand[t];
+        const bool push = live[t];
         const uint64_t m = __ballot(push);
         if (!m) continue;
         uint32_t base = 0;
@@ -374,108 +442,185 @@ __device__ __forceinline__ void lex_min(float &bd, int32_t &bi, float od, int32_
     }
 }
 
+// Wave-cooperative exact nearest-point search for one sample (every lane
+// holds the same sample).  On return (bd, bi) is the lexicographic minimum
+// (squared distance, point row) over all points with distance^2 <= the
+// initial bd, unless `retire` is set and the bound fell below M (then the
+// function returns true early and (bd, bi) is only an upper bound).
+__device__ bool ring_search(const GridParam &g, const uint32_t *__restrict__ cs, const float4 *__restrict__ xs,
+                            float sx, float sy, float sz, float &bd, int32_t &bi, bool retire, float &M,
+                            const uint64_t *__restrict__ keyj, uint32_t *s_p0, uint32_t *s_end, int lane,
+                            unsigned long long &nev) {
+    if (retire && sqrt_rn(bd) < M) return true;
+    const int cy = cell_of(sy, g.oy, g.inv_h, g.ny), cz = cell_of(sz, g.oz, g.inv_h, g.nz);
+    const int rmax = max(max(cy, g.ny - 1 - cy), max(cz, g.nz - 1 - cz));
+    const float h = g.h, eps = g.eps;
+    for (int base = 0;; base += 64) {
+        int r0, dy0, dz0;
+        ring_pos(base, r0, dy0, dz0);
+        if (r0 > rmax) break;
+        const float lbr = fmaxf((float)(r0 - 1) * h - eps, 0.f);
+        if (lbr * lbr > bd) break;
+        int r, dy, dz;
+        ring_pos(base + lane, r, dy, dz);
+        const int y = cy + dy, z = cz + dz;
+        uint32_t p0 = 0, cnt = 0;
+        if (r <= rmax && y >= 0 && y < g.ny && z >= 0 && z < g.nz) {
+            const float ez = fmaxf(fmaxf((g.oz + (float)z * h - eps) - sz, sz - (g.oz + (float)(z + 1) * h + eps)), 0.f);
+            const float ey = fmaxf(fmaxf((g.oy + (float)y * h - eps) - sy, sy - (g.oy + (float)(y + 1) * h + eps)), 0.f);
+            const float lzy = ez * ez + ey * ey;
+            if (!(lzy > bd)) {
+                const float w = sqrtf(fmaxf(bd - lzy, 0.f)) + eps;
+                const int x0 = cell_of(sx - w, g.ox, g.inv_h, g.nx);
+                const int x1 = cell_of(sx + w, g.ox, g.inv_h, g.nx);
+                const int64_t c0 = g.cell_base + ((int64_t)z * g.ny + y) * g.nx;
+                p0 = cs[c0 + x0];
+                cnt = cs[c0 + x1 + 1] - p0;
+            }
+        }
+        // flatten the 64 rows' points; each lane takes kU consecutive ones
+        uint32_t incl = cnt;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const uint32_t v = __shfl_up(incl, o, 64);
+            if (lane >= o) incl += v;
+        }
+        const uint32_t total = __builtin_amdgcn_readlane(incl, 63);
+        s_p0[lane] = p0;
+        s_end[lane] = incl;
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        float lbd = bd;
+        int32_t lbi = bi;
+        if (lane == 0) nev += total;
+        for (uint32_t k0 = (uint32_t)lane * kU; k0 < total; k0 += 64 * kU) {
+            int rr = 0, hi_r = 63;  // first row whose inclusive end exceeds k0
+            while (rr < hi_r) {
+                const int mid = (rr + hi_r) >> 1;
+                if (s_end[mid] > k0) hi_r = mid;
+                else rr = mid + 1;
+            }
+            uint32_t pp[kU];
+#pragma unroll
+            for (int u = 0; u < kU; ++u) {
+                const uint32_t kk = k0 + u;
+                pp[u] = 0xffffffffu;
+                if (kk < total) {
+                    while (s_end[rr] <= kk) ++rr;
+                    pp[u] = s_p0[rr] + (kk - (rr ? s_end[rr - 1] : 0u));
+                }
+            }
+            float4 cc[kU];
+#pragma unroll
+            for (int u = 0; u < kU; ++u)
+                if (pp[u] != 0xffffffffu) cc[u] = xs[pp[u]];
+#pragma unroll
+            for (int u = 0; u < kU; ++u)
+                if (pp[u] != 0xffffffffu)
+                    lex_min(lbd, lbi, dist2(sx, sy, sz, cc[u].x, cc[u].y, cc[u].z), __float_as_int(cc[u].w));
+        }
+        __builtin_amdgcn_wave_barrier();
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            const float od = __shfl_xor(lbd, o, 64);
+            const int32_t oi = __shfl_xor(lbi, o, 64);
+            lex_min(lbd, lbi, od, oi);
+        }
+        bd = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(lbd)));
+        bi = __builtin_amdgcn_readfirstlane(lbi);
+        if (retire) {
+            if ((base & 511) == 448)
+                M = fmaxf(M, key_value(__hip_atomic_load(keyj, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)));
+            if (sqrt_rn(bd) < M) return true;
+        }
+    }
+    return false;
+}
+
+__device__ __forceinline__ int find_cloud(const int64_t *__restrict__ s_off, int32_t B, int64_t j) {
+    int lo_b = 0, hi_b = B;
+    while (hi_b - lo_b > 1) {
+        const int mid = (lo_b + hi_b) >> 1;
+        if (s_off[mid] <= j) lo_b = mid;
+        else hi_b = mid;
+    }
+    return lo_b;
+}
+
+static constexpr uint32_t kGrab = 4;  // queue entries a wave takes per atomic
+
 __global__ __launch_bounds__(kWaveBlock) void k_flood_deep(
     DeepArgs a, const float *__restrict__ L, const int32_t *__restrict__ simp, const int64_t *__restrict__ s_off,
     const float *__restrict__ seed, uint64_t *__restrict__ key, const GridParam *__restrict__ gp,
     const uint32_t *__restrict__ cs, const float4 *__restrict__ xs, const uint64_t *__restrict__ queue,
-    const uint32_t *__restrict__ queue_count, uint32_t *__restrict__ queue_next, int32_t *__restrict__ xstar,
+    const uint32_t *__restrict__ queue_count, uint32_t *__restrict__ queue_next,
     unsigned long long *__restrict__ evals, unsigned long long *__restrict__ stats) {
-    const int lane = threadIdx.x & 63;
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    __shared__ uint32_t s_p0[kWaveBlock / 64][64], s_end[kWaveBlock / 64][64];
     const uint32_t n = *queue_count;
     if (stats && blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(&stats[4 * a.d + 1], (unsigned long long)n);
     unsigned long long nev = 0;
     while (true) {
-        uint32_t i = 0;
-        if (lane == 0) i = atomicAdd(queue_next, 1u);
-        i = __builtin_amdgcn_readfirstlane(i);
-        if (i >= n) break;
-        const uint64_t e = queue[i];
-        const uint32_t gid = (uint32_t)(e >> 32);
-        float bd = __uint_as_float((uint32_t)e);
-        int32_t bi = 0x7fffffff;
-        const int64_t j = gid / (uint32_t)a.n_int;
-        const int q = (int)(gid % (uint32_t)a.n_int);
-        int lo_b = 0, hi_b = a.B;
-        while (hi_b - lo_b > 1) {
-            int mid = (lo_b + hi_b) >> 1;
-            if (s_off[mid] <= j) lo_b = mid;
-            else hi_b = mid;
-        }
-        const GridParam g = gp[lo_b];
-        int comp[4];
-        if (a.d == 0) comp[0] = a.k;
-        else unrank_interior(q, a.d, a.k, comp);
-        int32_t v[4];
-        simplex_vertices(simp, a.d, j, v);
-        float sx, sy, sz;
-        sample_point(L, v, comp, a.d, a.k, sx, sy, sz);
-        const float sd = seed[j];
-        float M = fmaxf(sd, key_value(__hip_atomic_load(&key[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)));
-        bool retired = a.d > 0 && __fsqrt_rn(bd) < M;
-        const int cy = cell_of(sy, g.oy, g.inv_h, g.ny), cz = cell_of(sz, g.oz, g.inv_h, g.nz);
-        const int rmax = max(max(cy, g.ny - 1 - cy), max(cz, g.nz - 1 - cz));
-        const float h = g.h, eps = g.eps;
-        for (int base = 0; !retired; base += 64) {
-            int r0, dy0, dz0;
-            ring_pos(base, r0, dy0, dz0);
-            if (r0 > rmax) break;
-            const float lbr = fmaxf((float)(r0 - 1) * h - eps, 0.f);
-            if (lbr * lbr > bd) break;
-            int r, dy, dz;
-            ring_pos(base + lane, r, dy, dz);
-            const int y = cy + dy, z = cz + dz;
-            float lbd = bd;
-            int32_t lbi = bi;
-            if (r <= rmax && y >= 0 && y < g.ny && z >= 0 && z < g.nz) {
-                const float ez = fmaxf(fmaxf((g.oz + (float)z * h - eps) - sz, sz - (g.oz + (float)(z + 1) * h + eps)), 0.f);
-                const float ey = fmaxf(fmaxf((g.oy + (float)y * h - eps) - sy, sy - (g.oy + (float)(y + 1) * h + eps)), 0.f);
-                const float lzy = ez * ez + ey * ey;
-                if (!(lzy > bd)) {
-                    const float w = sqrtf(fmaxf(bd - lzy, 0.f)) + eps;
-                    const int x0 = cell_of(sx - w, g.ox, g.inv_h, g.nx);
-                    const int x1 = cell_of(sx + w, g.ox, g.inv_h, g.nx);
-                    const int64_t c0 = g.cell_base + ((int64_t)z * g.ny + y) * g.nx;
-                    const uint32_t p0 = cs[c0 + x0], p1 = cs[c0 + x1 + 1];
-                    nev += p1 - p0;
-                    uint32_t p = p0;
-                    for (; p + 1 < p1; p += 2) {
-                        const float4 c = xs[p], c2 = xs[p + 1];
-                        lex_min(lbd, lbi, dist2(sx, sy, sz, c.x, c.y, c.z), __float_as_int(c.w));
-                        lex_min(lbd, lbi, dist2(sx, sy, sz, c2.x, c2.y, c2.z), __float_as_int(c2.w));
-                    }
-                    if (p < p1) {
-                        const float4 c = xs[p];
-                        lex_min(lbd, lbi, dist2(sx, sy, sz, c.x, c.y, c.z), __float_as_int(c.w));
-                    }
-                }
-            }
-#pragma unroll
-            for (int o = 32; o > 0; o >>= 1) {
-                const float od = __shfl_xor(lbd, o, 64);
-                const int32_t oi = __shfl_xor(lbi, o, 64);
-                lex_min(lbd, lbi, od, oi);
-            }
-            bd = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(lbd)));
-            bi = __builtin_amdgcn_readfirstlane(lbi);
-            if (a.d > 0) {
-                if ((base & 511) == 448)
-                    M = fmaxf(M, key_value(__hip_atomic_load(&key[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)));
-                retired = __fsqrt_rn(bd) < M;
-            }
-        }
-        if (!retired && lane == 0) {
-            const float vv = __fsqrt_rn(bd);
-            if (a.d == 0 || vv > sd) {
-                xstar[gid] = bi;
-                const uint64_t nk = ((uint64_t)__float_as_uint(vv) << 32) | (uint64_t)(0xffffffffu - (uint32_t)q);
-                atomicMax((unsigned long long *)&key[j], (unsigned long long)nk);
-            }
+        uint32_t i0 = 0;
+        if (lane == 0) i0 = atomicAdd(queue_next, kGrab);
+        i0 = __builtin_amdgcn_readfirstlane(i0);
+        if (i0 >= n) break;
+        for (uint32_t i = i0; i < min(n, i0 + kGrab); ++i) {
+            const uint64_t e = queue[i];
+            const uint32_t gid = (uint32_t)(e >> 32);
+            float bd = __uint_as_float((uint32_t)e);
+            int32_t bi = 0x7fffffff;
+            const int64_t j = gid / (uint32_t)a.n_int;
+            const int q = (int)(gid % (uint32_t)a.n_int);
+            const GridParam g = gp[find_cloud(s_off, a.B, j)];
+            int comp[4];
+            if (a.d == 0) comp[0] = a.k;
+            else unrank_interior(q, a.d, a.k, comp);
+            int32_t v[4];
+            simplex_vertices(simp, a.d, j, v);
+            float sx, sy, sz;
+            sample_point(L, v, comp, a.d, a.k, sx, sy, sz);
+            float M = fmaxf(seed[j], key_value(__hip_atomic_load(&key[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)));
+            const bool retired = ring_search(g, cs, xs, sx, sy, sz, bd, bi, a.d > 0, M, &key[j], s_p0[wid],
+                                             s_end[wid], lane, nev);
+            if (!retired && lane == 0) publish(key, seed, (int32_t)j, q, bd, a.d == 0);
         }
     }
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) nev += __shfl_xor(nev, o, 64);
     if (evals && lane == 0 && nev) atomicAdd(evals, nev);
     if (stats && lane == 0 && nev) atomicAdd(&stats[4 * a.d + 3], nev);
+}
+
+// x* of the winning own sample of every simplex (one wave per simplex): the
+// value is known, so the search ball is exact and tiny for most simplices
+__global__ __launch_bounds__(kWaveBlock) void k_winner_search(
+    int d, int k, int64_t n, int32_t B, const float *__restrict__ L, const int32_t *__restrict__ simp,
+    const int64_t *__restrict__ s_off, const uint64_t *__restrict__ key, const GridParam *__restrict__ gp,
+    const uint32_t *__restrict__ cs, const float4 *__restrict__ xs, int32_t *__restrict__ win_x) {
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    __shared__ uint32_t s_p0[kWaveBlock / 64][64], s_end[kWaveBlock / 64][64];
+    const int64_t j = (int64_t)blockIdx.x * (blockDim.x >> 6) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    if (j >= n) return;
+    const uint64_t kv = key[j];
+    if (kv == 0) return;
+    const int q = (int)(0xffffffffu - (uint32_t)(kv & 0xffffffffu));
+    int comp[4];
+    if (d == 0) comp[0] = k;
+    else unrank_interior(q, d, k, comp);
+    int32_t v[4];
+    simplex_vertices(simp, d, j, v);
+    float sx, sy, sz;
+    sample_point(L, v, comp, d, k, sx, sy, sz);
+    const float val = key_value(kv);
+    const float rb = val * (1.0f + 1e-6f) + 1e-30f;
+    float bd = rb * rb;
+    int32_t bi = 0x7fffffff;
+    float M = 0.f;
+    unsigned long long nev = 0;
+    const GridParam g = gp[find_cloud(s_off, B, j)];
+    ring_search(g, cs, xs, sx, sy, sz, bd, bi, false, M, nullptr, s_p0[wid], s_end[wid], lane, nev);
+    if (lane == 0) win_x[j] = bi;
 }
 
 // ---------------------------------------------------------------------------
@@ -487,10 +632,9 @@ __device__ __forceinline__ uint32_t pack_comp(const int a[4]) {
     return (uint32_t)a[0] | ((uint32_t)a[1] << 8) | ((uint32_t)a[2] << 16) | ((uint32_t)a[3] << 24);
 }
 
-__global__ void k_winner(int d, int k, int64_t n, int n_int, const int32_t *__restrict__ simp,
+__global__ void k_winner(int d, int k, int64_t n, const int32_t *__restrict__ simp,
                          const int32_t *__restrict__ tri_edges, const int32_t *__restrict__ tet_tris,
-                         const float *__restrict__ seed, const uint64_t *__restrict__ key,
-                         const int32_t *__restrict__ xstar, const float *__restrict__ fprev,
+                         const float *__restrict__ seed, const uint64_t *__restrict__ key, const float *__restrict__ fprev,
                          const int32_t *__restrict__ wxprev, const uint32_t *__restrict__ waprev,
                          float *__restrict__ f, int32_t *__restrict__ win_x, uint32_t *__restrict__ win_a) {
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -502,8 +646,7 @@ __global__ void k_winner(int d, int k, int64_t n, int n_int, const int32_t *__re
         if (d == 0) comp[0] = k;
         else unrank_interior(q, d, k, comp);
         f[j] = key_value(kv);
-        win_x[j] = xstar[j * (int64_t)n_int + q];
-        win_a[j] = pack_comp(comp);
+        win_a[j] = pack_comp(comp);  // win_x comes from k_winner_search
         return;
     }
     const float sd = seed[j];
@@ -546,7 +689,17 @@ size_t flood_workspace(const flood_problem *pb, float alpha, FloodSizes *sz) {
     bytes += sizeof(float) * (nmax + 1) + 256;        // seed
     bytes += sizeof(uint64_t) * (nmax + 1) + 256;     // key
     bytes += sizeof(uint64_t) * (smax + 1) + 256;     // open-sample queue
-    bytes += sizeof(int32_t) * (smax + 1) + 256;      // x* of candidate samples
+    int64_t bkmax = 0;
+    for (int d = 0; d < 4; ++d) {
+        int64_t bk = 0;
+        const int64_t *so = d == 0 ? pb->l_off : pb->s_off[d];
+        for (int32_t b = 0; b < pb->B; ++b) bk += (int64_t)1 << (3 * morton_bits((so[b + 1] - so[b]) * n_interior(d, pb->k)));
+        bkmax = bk > bkmax ? bk : bkmax;
+    }
+    bytes += 2 * (sizeof(uint32_t) * (smax + 1) + 256);  // sample keys and order
+    bytes += 2 * (sizeof(uint32_t) * (bkmax + 1) + 256); // bucket counts and cursors
+    bytes += sizeof(uint32_t) * scan_tmp_elems(bkmax + 1) + 256;
+    bytes += sizeof(int32_t) * (pb->B + 1) + sizeof(uint32_t) * (pb->B + 1) + 512;
     bytes += sizeof(uint32_t) * 8 + 256;              // queue counters
     bytes += 4 * (sizeof(int64_t) * (pb->B + 1) + 256); // tile offsets
     bytes += 1024;
@@ -561,10 +714,11 @@ size_t flood_workspace(const flood_problem *pb, float alpha, FloodSizes *sz) {
 template <int T>
 static void launch_tiles(const TileArgs &ta, int wpb, hipStream_t s, const float *L, const int32_t *simp,
                          const int64_t *s_off, const int64_t *tile_off, const float *seed, uint64_t *key,
-                         const GridWork &g, uint64_t *hard, uint32_t *hard_count, uint64_t *evals, uint64_t *stats) {
+                         const GridWork &g, const uint32_t *order, uint64_t *hard, uint32_t *hard_count,
+                         uint64_t *evals, uint64_t *stats) {
     const int64_t nb = (ta.n_tiles + wpb - 1) / wpb;
     hipLaunchKernelGGL(k_flood_tiles<T>, dim3((unsigned)nb), dim3(64 * wpb), 0, s, ta, L, simp, s_off, tile_off,
-                       seed, key, g.gp, g.cell_start, g.xs, hard, hard_count, (unsigned long long *)evals,
+                       seed, key, g.gp, g.cell_start, g.xs, order, hard, hard_count, (unsigned long long *)evals,
                        (unsigned long long *)stats);
 }
 
@@ -585,8 +739,21 @@ hipError_t flood_run(const flood_problem *pb, const flood_tuning &tu, const floo
     float *seed = c.take<float>(nmax + 1);
     uint64_t *key = c.take<uint64_t>(nmax + 1);
     uint64_t *hard = c.take<uint64_t>(smax + 1);
-    int32_t *xstar = c.take<int32_t>(smax + 1);
     uint32_t *counters = c.take<uint32_t>(8);
+    int64_t bkmax = 0;
+    for (int d = 0; d < 4; ++d) {
+        int64_t bk = 0;
+        const int64_t *so = d == 0 ? pb->l_off : pb->s_off[d];
+        for (int32_t b = 0; b < pb->B; ++b) bk += (int64_t)1 << (3 * morton_bits((so[b + 1] - so[b]) * n_interior(d, pb->k)));
+        bkmax = bk > bkmax ? bk : bkmax;
+    }
+    uint32_t *skey = c.take<uint32_t>(smax + 1);
+    uint32_t *order = c.take<uint32_t>(smax + 1);
+    uint32_t *bcount = c.take<uint32_t>(bkmax + 1);
+    uint32_t *bcursor = c.take<uint32_t>(bkmax + 1);
+    uint32_t *bscan = c.take<uint32_t>(scan_tmp_elems(bkmax + 1));
+    int32_t *mbits = c.take<int32_t>(pb->B + 1);
+    uint32_t *bbase = c.take<uint32_t>(pb->B + 1);
     int64_t *tile_off[4];
     for (int d = 0; d < 4; ++d) tile_off[d] = c.take<int64_t>(pb->B + 1);
     if (!c.ok()) return hipErrorOutOfMemory;
@@ -613,6 +780,21 @@ hipError_t flood_run(const flood_problem *pb, const flood_tuning &tu, const floo
             int64_t ntiles = 0;
             for (int32_t b = 0; b < pb->B; ++b) ntiles += ((soff_h[b + 1] - soff_h[b]) * nint + tsamp - 1) / tsamp;
             hipLaunchKernelGGL(k_tile_off, dim3(1), dim3(1), 0, s, soff_d, pb->B, nint, tsamp, tile_off[d]);
+            // spatial order of the samples
+            int64_t bk = 0;
+            for (int32_t b = 0; b < pb->B; ++b) bk += (int64_t)1 << (3 * morton_bits((soff_h[b + 1] - soff_h[b]) * nint));
+            const int64_t S = n * nint;
+            hipLaunchKernelGGL(k_bucket_base, dim3(1), dim3(1), 0, s, soff_d, pb->B, nint, mbits, bbase);
+            e = fill_u32(bcount, 0u, bk + 1, s);
+            if (e != hipSuccess) return e;
+            hipLaunchKernelGGL(k_sample_keys, dim3((unsigned)((S + 255) / 256)), dim3(256), 0, s, d, pb->k, (int)nint,
+                               pb->B, S, pb->Lxyz, simp, soff_d, g.gp, mbits, bbase, skey, bcount);
+            e = exclusive_scan_u32(bcount, bk + 1, bscan, s);
+            if (e != hipSuccess) return e;
+            e = copy_u32(bcount, bcursor, bk, s);
+            if (e != hipSuccess) return e;
+            hipLaunchKernelGGL(k_sample_scatter, dim3((unsigned)((S + 255) / 256)), dim3(256), 0, s, S, skey, bcursor,
+                               order);
             if (ntiles > 0) {
                 TileArgs ta;
                 ta.d = d;
@@ -621,34 +803,40 @@ hipError_t flood_run(const flood_problem *pb, const flood_tuning &tu, const floo
                 ta.landmarks_in_x = pb->landmarks_in_x;
                 ta.B = pb->B;
                 ta.radius_budget = tu.tile_shells - 1;  // -2 disables the cooperative phase
-                ta.max_extent = 8;
+                ta.max_extent = tu.tile_extent;
                 ta.pad = 0;
                 ta.n_tiles = ntiles;
-                if (out->tile_events[2 * d]) {
-                    e = hipEventRecord((hipEvent_t)out->tile_events[2 * d], s);
+                if (out->tile_events[3 * d]) {
+                    e = hipEventRecord((hipEvent_t)out->tile_events[3 * d], s);
                     if (e != hipSuccess) return e;
                 }
-                if (T == 1) launch_tiles<1>(ta, wpb, s, pb->Lxyz, simp, soff_d, tile_off[d], seed, key, g, hard, counters, out->evals, out->stats);
-                else if (T == 2) launch_tiles<2>(ta, wpb, s, pb->Lxyz, simp, soff_d, tile_off[d], seed, key, g, hard, counters, out->evals, out->stats);
-                else launch_tiles<4>(ta, wpb, s, pb->Lxyz, simp, soff_d, tile_off[d], seed, key, g, hard, counters, out->evals, out->stats);
+                if (T == 1) launch_tiles<1>(ta, wpb, s, pb->Lxyz, simp, soff_d, tile_off[d], seed, key, g, order, hard, counters, out->evals, out->stats);
+                else if (T == 2) launch_tiles<2>(ta, wpb, s, pb->Lxyz, simp, soff_d, tile_off[d], seed, key, g, order, hard, counters, out->evals, out->stats);
+                else launch_tiles<4>(ta, wpb, s, pb->Lxyz, simp, soff_d, tile_off[d], seed, key, g, order, hard, counters, out->evals, out->stats);
+                if (out->tile_events[3 * d + 1]) {
+                    e = hipEventRecord((hipEvent_t)out->tile_events[3 * d + 1], s);
+                    if (e != hipSuccess) return e;
+                }
                 DeepArgs da;
                 da.d = d;
                 da.k = pb->k;
                 da.n_int = (int32_t)nint;
                 da.B = pb->B;
                 hipLaunchKernelGGL(k_flood_deep, dim3(2048), dim3(256), 0, s, da, pb->Lxyz, simp, soff_d, seed, key,
-                                   g.gp, g.cell_start, g.xs, hard, counters, counters + 1, xstar,
+                                   g.gp, g.cell_start, g.xs, hard, counters, counters + 1,
                                    (unsigned long long *)out->evals, (unsigned long long *)out->stats);
-                if (out->tile_events[2 * d + 1]) {
-                    e = hipEventRecord((hipEvent_t)out->tile_events[2 * d + 1], s);
+                if (out->tile_events[3 * d + 2]) {
+                    e = hipEventRecord((hipEvent_t)out->tile_events[3 * d + 2], s);
                     if (e != hipSuccess) return e;
                 }
             }
         }
-        hipLaunchKernelGGL(k_winner, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, d, pb->k, n, (int)nint,
-                           simp, pb->tri_edges, pb->tet_tris, seed, key, xstar, d > 0 ? out->f[d - 1] : nullptr,
+        hipLaunchKernelGGL(k_winner, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, d, pb->k, n, simp,
+                           pb->tri_edges, pb->tet_tris, seed, key, d > 0 ? out->f[d - 1] : nullptr,
                            d > 0 ? out->win_x[d - 1] : nullptr, d > 0 ? out->win_a[d - 1] : nullptr, out->f[d],
                            out->win_x[d], out->win_a[d]);
+        hipLaunchKernelGGL(k_winner_search, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, s, d, pb->k, n, pb->B,
+                           pb->Lxyz, simp, soff_d, key, g.gp, g.cell_start, g.xs, out->win_x[d]);
         e = hipGetLastError();
         if (e != hipSuccess) return e;
     }

@@ -37,6 +37,15 @@ hipError_t fill_u64(uint64_t *p, uint64_t v, int64_t n, hipStream_t s) {
     hipLaunchKernelGGL(k_fill_u64, dim3(grid_blocks(n)), dim3(kBlock), 0, s, p, v, n);
     return hipGetLastError();
 }
+__global__ void k_copy_u32b(const uint32_t *src, uint32_t *dst, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        dst[i] = src[i];
+}
+hipError_t copy_u32(const uint32_t *src, uint32_t *dst, int64_t n, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_copy_u32b, dim3(grid_blocks(n)), dim3(kBlock), 0, s, src, dst, n);
+    return hipGetLastError();
+}
 hipError_t fill_f32(float *p, float v, int64_t n, hipStream_t s) {
     if (n <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_fill_f32, dim3(grid_blocks(n)), dim3(kBlock), 0, s, p, v, n);
@@ -211,7 +220,7 @@ __global__ __launch_bounds__(kBlock) void k_bbox(const float *X, const int64_t *
 
 // one thread: grid parameters of every cloud (sequential prefix of the cell bases)
 __global__ void k_grid_params(const uint32_t *bbox, const int64_t *x_off, int32_t B, float alpha, int32_t max_dim,
-                              GridParam *gp) {
+                              int64_t morton_lo, int64_t morton_hi, GridParam *gp) {
     if (blockIdx.x != 0 || threadIdx.x != 0) return;
     int64_t base = 0;
     for (int32_t b = 0; b < B; ++b) {
@@ -235,19 +244,27 @@ __global__ void k_grid_params(const uint32_t *bbox, const int64_t *x_off, int32_
         double h = cbrt(vol / target);
         if (!(h > 0.0)) h = emax;
         int64_t nx, ny, nz;
-        for (int it = 0; it < 4096; ++it) {
-            nx = (int64_t)floor((double)e[0] / h) + 1;
-            ny = (int64_t)floor((double)e[1] / h) + 1;
-            nz = (int64_t)floor((double)e[2] / h) + 1;
-            if (nx <= max_dim && ny <= max_dim && nz <= max_dim && nx * ny * nz <= cap) break;
-            h *= 1.05;
+        g.morton = (n >= morton_lo && n < morton_hi) ? 1 : 0;
+        if (g.morton) {
+            // a 2^m cube over the largest extent, 8^m <= cap - 64 cells
+            int m = 0;
+            while (m < 10 && ((int64_t)8 << (3 * m)) <= cap - 64 && ((int64_t)2 << m) <= max_dim) ++m;
+            nx = ny = nz = (int64_t)1 << m;
+            h = (double)emax / (double)nx;
+        } else {
+            for (int it = 0; it < 4096; ++it) {
+                nx = (int64_t)floor((double)e[0] / h) + 1;
+                ny = (int64_t)floor((double)e[1] / h) + 1;
+                nz = (int64_t)floor((double)e[2] / h) + 1;
+                if (nx <= max_dim && ny <= max_dim && nz <= max_dim && nx * ny * nz <= cap) break;
+                h *= 1.05;
+            }
         }
         g.ox = lo[0]; g.oy = lo[1]; g.oz = lo[2];
         g.h = (float)h;
         g.inv_h = (float)(1.0 / h);
         g.eps = 1e-3f * (float)h + 1e-6f * amax;
         g.nx = (int32_t)nx; g.ny = (int32_t)ny; g.nz = (int32_t)nz;
-        g.pad = 0;
         g.cell_base = base;
         g.pt_base = x_off[b];
         g.npts = n;
@@ -266,7 +283,8 @@ __global__ __launch_bounds__(kBlock) void k_count(const float *X, const GridPara
         int cx = bin_coord(X[3 * i], g.ox, g.inv_h, g.nx);
         int cy = bin_coord(X[3 * i + 1], g.oy, g.inv_h, g.ny);
         int cz = bin_coord(X[3 * i + 2], g.oz, g.inv_h, g.nz);
-        uint32_t c = (uint32_t)(g.cell_base + ((int64_t)cz * g.ny + cy) * g.nx + cx);
+        const uint32_t c = g.morton ? (uint32_t)g.cell_base + (spread3(cx) | (spread3(cy) << 1) | (spread3(cz) << 2))
+                                    : (uint32_t)(g.cell_base + ((int64_t)cz * g.ny + cy) * g.nx + cx);
         pcell[i] = c;
         atomicAdd(&counts[c], 1u);
     }
@@ -289,7 +307,7 @@ __global__ __launch_bounds__(kBlock) void k_scatter(const float *X, const GridPa
 }
 
 hipError_t grid_build(const float *X, int32_t B, const int64_t *x_off, const int64_t *x_off_d,
-                      float alpha, GridWork &g, hipStream_t s, int32_t max_dim) {
+                      float alpha, GridWork &g, hipStream_t s, int32_t max_dim, int64_t morton_lo, int64_t morton_hi) {
     int64_t nmax = 0;
     for (int32_t b = 0; b < B; ++b) nmax = nmax > x_off[b + 1] - x_off[b] ? nmax : x_off[b + 1] - x_off[b];
     int bx = (int)((nmax + kBlock * 8 - 1) / (kBlock * 8));
@@ -297,7 +315,7 @@ hipError_t grid_build(const float *X, int32_t B, const int64_t *x_off, const int
     if (bx > 4096) bx = 4096;
     hipLaunchKernelGGL(k_bbox_init, dim3((6 * B + 255) / 256), dim3(256), 0, s, g.bbox, B);
     hipLaunchKernelGGL(k_bbox, dim3(bx, B), dim3(kBlock), 0, s, X, x_off_d, g.bbox);
-    hipLaunchKernelGGL(k_grid_params, dim3(1), dim3(1), 0, s, g.bbox, x_off_d, B, alpha, max_dim, g.gp);
+    hipLaunchKernelGGL(k_grid_params, dim3(1), dim3(1), 0, s, g.bbox, x_off_d, B, alpha, max_dim, morton_lo, morton_hi, g.gp);
     hipError_t e = fill_u32(g.cell_start, 0u, g.total_cells + 1, s);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_count, dim3(bx, B), dim3(kBlock), 0, s, X, g.gp, g.pcell, g.cell_start);

@@ -9,14 +9,17 @@
 namespace flood {
 
 // Per-cloud uniform grid.  Cell (ix,iy,iz) of cloud b is global cell
-// cell_base + (iz*ny + iy)*nx + ix; cell_start[] holds global positions in
-// the cell-sorted point array, so one exclusive scan serves every cloud.
+// cell_base + (iz*ny + iy)*nx + ix, or cell_base + morton(ix,iy,iz) on a
+// 2^m cube when `morton` is set (landmark grids of large clouds, whose
+// sorted order must be spatially compact); cell_start[] holds global
+// positions in the cell-sorted point array, so one exclusive scan serves
+// every cloud.
 struct GridParam {
     float ox, oy, oz;   // grid origin (bbox minimum)
     float h, inv_h;     // cell edge and its reciprocal
     float eps;          // slack added around cell boxes (covers rounding of the binning)
     int32_t nx, ny, nz; // cells per axis
-    int32_t pad;
+    int32_t morton;     // 1: cells numbered in Morton order (nx = ny = nz = 2^m)
     int64_t cell_base;  // first global cell of this cloud
     int64_t pt_base;    // first global point of this cloud
     int64_t npts;
@@ -53,6 +56,16 @@ __device__ inline float key_float(uint32_t k) {
     return __uint_as_float(u);
 }
 
+// 10-bit value with its bits spread to every third position (Morton codes)
+__device__ __forceinline__ uint32_t spread3(uint32_t v) {
+    v &= 0x3ff;
+    v = (v | (v << 16)) & 0x030000ff;
+    v = (v | (v << 8)) & 0x0300f00f;
+    v = (v | (v << 4)) & 0x030c30c3;
+    v = (v | (v << 2)) & 0x09249249;
+    return v;
+}
+
 // cell coordinate of a coordinate value (the binning rule; NaN maps to 0)
 __device__ inline int bin_coord(float v, float o, float inv_h, int n) {
     float t = (v - o) * inv_h;
@@ -75,12 +88,14 @@ struct GridWork {
 size_t grid_workspace(int32_t B, const int64_t *x_off, float alpha, int64_t *total_cells);
 void grid_carve(Carve &c, int32_t B, int64_t total_pts, int64_t total_cells, GridWork &g);
 hipError_t grid_build(const float *X, int32_t B, const int64_t *x_off, const int64_t *x_off_d,
-                      float alpha, GridWork &g, hipStream_t s, int32_t max_dim = 1 << 20);
+                      float alpha, GridWork &g, hipStream_t s, int32_t max_dim = 1 << 20,
+                      int64_t morton_lo = INT64_MAX, int64_t morton_hi = INT64_MAX);
 
 // generic helpers (grid.hip)
 hipError_t fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s);
 hipError_t fill_u64(uint64_t *p, uint64_t v, int64_t n, hipStream_t s);
 hipError_t fill_f32(float *p, float v, int64_t n, hipStream_t s);
+hipError_t copy_u32(const uint32_t *src, uint32_t *dst, int64_t n, hipStream_t s);
 hipError_t exclusive_scan_u32(uint32_t *data, int64_t n, uint32_t *tmp, hipStream_t s);
 size_t scan_tmp_elems(int64_t n);
 

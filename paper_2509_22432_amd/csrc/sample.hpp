@@ -6,6 +6,21 @@
 
 namespace flood {
 
+// Morton resolution (bits per axis) of the sample sort: about four samples
+// per bucket on a 2^m cube
+__host__ __device__ inline int morton_bits(int64_t S) {
+    int m = 1;
+    while (m < 8 && ((int64_t)4 << (3 * m)) < S) ++m;
+    return m;
+}
+
+// correctly rounded float square root.  The rounded-sqrt intrinsic of the
+// HIP headers lowers to the approximate hardware instruction unless the
+// rounded-operation macros are defined, which made flood values depend on
+// the kernel that published them; the builtin is lowered with the exact
+// correction steps.
+__device__ __forceinline__ float sqrt_rn(float x) { return __builtin_sqrtf(x); }
+
 __device__ __forceinline__ float dist2(float sx, float sy, float sz, float px, float py, float pz) {
     const float dx = sx - px, dy = sy - py, dz = sz - pz;
     return __fmaf_rn(dz, dz, __fmaf_rn(dy, dy, dx * dx));

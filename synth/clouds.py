@@ -189,3 +189,11 @@ def circle_points(n: int) -> np.ndarray:
     """n equally spaced points on the unit circle in the plane z=0 (float32)."""
     t = 2 * np.pi * np.arange(n) / n
     return np.ascontiguousarray(np.stack([np.cos(t), np.sin(t), np.zeros(n)], 1), dtype=np.float32)
+
+
+def lattice_points(side: int, seed: int = 7) -> np.ndarray:
+    """The integer lattice {0..side-1}^3 in a seeded random row order: every
+    distance is a small integer norm, so exact ties are everywhere."""
+    g = np.arange(side, dtype=np.float32)
+    X = np.stack(np.meshgrid(g, g, g, indexing="ij"), -1).reshape(-1, 3)
+    return np.ascontiguousarray(X[np.random.default_rng(seed).permutation(len(X))])

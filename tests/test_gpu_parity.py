@@ -26,7 +26,7 @@ def _maxerr_per_dim(res, ref):
 
 # ---------------------------------------------------------------- landmarks
 
-@pytest.mark.parametrize("cfg,n,L", [(1, None, 64), (2, 200_000, 700), (2, None, 2000)])
+@pytest.mark.parametrize("cfg,n,L", [(1, None, 64), (2, 200_000, 700), (2, None, 2000), (3, None, 10_000)])
 def test_fps_bitexact(cfg, n, L):
     X = synth.config_cloud(cfg, n)
     print("fps parity cfg", cfg, "N", len(X), "L", L, flush=True)
@@ -35,6 +35,20 @@ def test_fps_bitexact(cfg, n, L):
     oidx, orad = OP.fps(X, L)
     assert np.array_equal(idx.cpu().numpy(), oidx)
     assert np.array_equal(rad.cpu().numpy(), orad)
+
+
+def test_fps_lattice_ties_and_start():
+    # 531441 lattice points take the cooperative path; exact ties are decided
+    # by the lowest point index, and the first landmark is not point 0
+    X = synth.lattice_points(81)
+    print("fps lattice N", len(X), flush=True)
+    for start, L in ((12345, 600), (0, 64)):
+        idx, rad = P.fps(torch.from_numpy(X).to(dev()), L, start=start)
+        torch.cuda.synchronize()
+        oidx, orad = OP.fps(X, L, start=start)
+        assert idx.cpu().numpy()[0] == start
+        assert np.array_equal(idx.cpu().numpy(), oidx)
+        assert np.array_equal(rad.cpu().numpy(), orad)
 
 
 def test_fps_batched_bitexact():

@@ -58,9 +58,9 @@ def test_filtration_rejects_small_workspace_and_bad_tuning():
         out.f[d] = out.win_x[d] = out.win_a[d] = 0x2000
     L = _lib.lib()
     assert L.flood_filtration(ctypes.byref(pb), None, ctypes.byref(out), ctypes.c_void_p(0x3000), 16, None) == _lib.ENOMEM
-    t = _lib.Tuning(100.0, 1, 4, 0)
+    t = _lib.Tuning(100.0, 1, 4, 0, 0)
     assert L.flood_filtration(ctypes.byref(pb), ctypes.byref(t), ctypes.byref(out), None, 0, None) == _lib.EINVAL
-    t = _lib.Tuning(1.0, 3, 4, 0)
+    t = _lib.Tuning(1.0, 3, 4, 0, 0)
     assert L.flood_filtration(ctypes.byref(pb), ctypes.byref(t), ctypes.byref(out), None, 0, None) == _lib.EINVAL
 
 
