@@ -90,6 +90,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--batched-clouds", type=int, default=512, help="0 skips the batched block")
     ap.add_argument("--batched-scale", type=float, default=1.0)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a plain 1 GiB device copy three times (scale for the FETCH_SIZE / "
+                         "WRITE_SIZE counters) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the flooding path here is single-GPU "
@@ -97,6 +100,15 @@ def main():
         sys.exit(2)
 
     import torch
+    if args.calibrate_copy:
+        n = 1 << 28
+        x = torch.ones(n, device="cuda")
+        y = torch.empty_like(x)
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibrate_copy_bytes_per_launch": n * 4, "launches": 3}), flush=True)
+        return
     import paper_2509_22432_amd as P
     import synth
 
@@ -187,6 +199,8 @@ def main():
         "search_stats_per_dim": {"per_sample_search_samples": [int(v) for v in run.stats.view(4, 4)[:, 1].cpu()],
                                  "tile_evals": [int(v) for v in run.stats.view(4, 4)[:, 2].cpu()],
                                  "per_sample_evals": [int(v) for v in run.stats.view(4, 4)[:, 3].cpu()]},
+        "fps": {"ms": float(np.mean(fps_ms)), "rounds": args.n_landmarks,
+                "us_per_round": float(np.mean(fps_ms)) * 1e3 / args.n_landmarks},
         "stage_ms": {"fps": float(np.mean(fps_ms)), "filtration": float(np.mean(flood_ms)),
                      "tile_search_per_dim": [float(np.mean([t[d][0] for t in tile_ms])) for d in range(4)],
                      "per_sample_search_per_dim": [float(np.mean([t[d][1] for t in tile_ms])) for d in range(4)],

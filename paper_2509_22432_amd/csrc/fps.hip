@@ -12,7 +12,9 @@
 //   closer to the new landmark than the chunk's max minimum (a point
 //   farther away cannot change), re-reduces the workgroup's max, publishes
 //   it to a two-slot ring in global memory and polls the W slots of the
-//   round: the ring replaces a grid barrier and a second reduction.
+//   round: the ring replaces a grid barrier and a second reduction.  Only
+//   the 64-bit keys cross workgroups (the winner's coordinates are read
+//   from X), so no release/acquire fence and no L2 write-back is needed.
 // * Small clouds (batches): one persistent workgroup per cloud over a
 //   row-major grid.  State per row of cells and per z-slab of rows; a
 //   round updates the points in the cells within the covering radius R of
@@ -28,8 +30,8 @@ namespace flood {
 static constexpr int kDenseBlock = 256;
 static constexpr int kPT = 1024;       // persistent workgroup
 static constexpr int kU = 8;           // points per thread per step
-static constexpr int kMaxDim = 1024;
-static constexpr int kMaxWGRing = 1024;  // ring slots per round of the cooperative path   // cells per axis of an FPS grid (slab keys fit in LDS)
+static constexpr int kMaxDim = 1024;   // cells per axis of a row grid (slab keys fit in LDS)
+static constexpr int kMaxWG = 256;     // workgroups of one cooperative launch (ring slots per round)
 
 struct FpsState {
     int32_t cur;  // local index of the newest landmark
@@ -57,7 +59,7 @@ size_t fps_workspace(int32_t B, const int64_t *x_off, const int32_t *n_lm) {
     bytes += sizeof(uint64_t) * (tc + 1) + 256;
     bytes += sizeof(FpsState) * B + 256;
     bytes += sizeof(int64_t) * (B + 1) + 256;
-    bytes += (sizeof(uint64_t) + sizeof(float4)) * 2 * kMaxWGRing + 512;  // cooperative ring
+    bytes += sizeof(uint64_t) * 2 * kMaxWG + 256;  // cooperative ring
     bytes += sizeof(uint32_t) + 256;
     return bytes + 1024;
 }
@@ -432,10 +434,7 @@ __global__ __launch_bounds__(kPT) void k_fps_persist(
 // ---------------------------------------------------------------------------
 // cooperative rounds (large clouds)
 
-static constexpr int kCoopThreads = 256;
-static constexpr int kCoopWaves = kCoopThreads / 64;
-static constexpr int kMaxCpw = 3072;              // chunk slots per workgroup (48 B of LDS each)
-static constexpr int kMaxWG = kMaxWGRing;
+static constexpr int kMaxCpw = 4096;              // chunk slots per workgroup (36 B of LDS each)
 static constexpr int64_t kCoopMin = 1 << 19;      // clouds of at least this many points
 static constexpr int64_t kCoopMaxPts = 1 << 30;   // the ring key keeps 30 index bits
 static constexpr int kSpinLimit = 1 << 22;        // polls of one round before the launch gives up
@@ -443,7 +442,7 @@ static constexpr int kSpinLimit = 1 << 22;        // polls of one round before t
 struct CoopArgs {
     int32_t b;       // cloud
     int32_t nl;      // landmarks
-    int32_t nwg;     // workgroups W
+    int32_t nwg;     // working workgroups W
     int32_t pad;
     int64_t nchunk;  // chunks of 64*m points
     int64_t lo;      // first landmark slot of the cloud in idx/radius
@@ -466,27 +465,34 @@ __device__ __forceinline__ uint64_t ring_key(uint64_t k, uint32_t tag) {
     return (k & 0xffffffff00000000ull) | ((uint64_t)tag << 30) | (uint64_t)(0x3fffffffu - idx);
 }
 
-// LM = log2(m).  LDS per chunk slot: key, box (6 floats), argmax point, list entry.
+// LM = log2(m) points per lane per chunk.  Keys cross workgroups through
+// memory (agent-scope atomics: each XCD has its own L2); a stale slot never
+// carries the round's tag, so it only delays the poll.
+// LDS per chunk slot: max key, box (6 floats), list entry.
 template <int LM>
-__global__ __launch_bounds__(kCoopThreads) void k_fps_coop(
+__global__ __launch_bounds__(256) void k_fps_coop(
     CoopArgs a, const float *__restrict__ X, const GridParam *__restrict__ gp, const float4 *__restrict__ xs,
-    float *__restrict__ mind, uint64_t *__restrict__ rk, float4 *__restrict__ rp, uint32_t *__restrict__ err,
+    float *__restrict__ mind, uint64_t *__restrict__ rk, uint32_t *__restrict__ ctl,
     const int64_t *__restrict__ start, int32_t *__restrict__ idx_out, float *__restrict__ radius) {
+    constexpr int NT = 256;
+    constexpr int NW = NT / 64;
     constexpr int M = 1 << LM;     // points per lane per chunk
     constexpr int U = 8 >> LM;     // chunks per wave step
+    constexpr int PER = kMaxWG / 64;  // ring slots polled per lane
+    constexpr int SCOPE = __HIP_MEMORY_SCOPE_AGENT;
     extern __shared__ __align__(16) unsigned char smem[];
-    const int wg = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-    const int W = a.nwg;
-    const int nmine = (int)((a.nchunk - wg + W - 1) / W);  // chunk slots owned (wg < nchunk)
-    uint64_t *s_key = (uint64_t *)smem;
-    float *s_bb = (float *)(s_key + nmine);
-    float *s_px = s_bb + 6 * nmine;
-    uint32_t *s_list = (uint32_t *)(s_px + 3 * nmine);
     __shared__ float s_l[4];
     __shared__ uint32_t s_n;
     __shared__ int s_abort;
-    __shared__ uint64_t s_wk[kCoopWaves];
-    __shared__ int s_ws[kCoopWaves];
+    __shared__ uint64_t s_wk[NW];
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const int W = a.nwg;
+    const int wg = blockIdx.x;
+    uint32_t *err = &ctl[0];
+    const int nmine = (int)((a.nchunk - wg + W - 1) / W);  // chunk slots owned (W <= nchunk)
+    uint64_t *s_key = (uint64_t *)smem;
+    float *s_bb = (float *)(s_key + nmine);
+    uint32_t *s_list = (uint32_t *)(s_bb + 6 * nmine);
 
     const GridParam g = gp[a.b];
     const int64_t pb = g.pt_base, npts = g.npts;
@@ -510,7 +516,7 @@ __global__ __launch_bounds__(kCoopThreads) void k_fps_coop(
         } else {
             if (tid == 0) s_n = 0;
             __syncthreads();
-            for (int s0 = 0; s0 < nmine; s0 += kCoopThreads) {
+            for (int s0 = 0; s0 < nmine; s0 += NT) {
                 const int sl = s0 + tid;
                 bool hit = false;
                 if (sl < nmine) {
@@ -528,7 +534,7 @@ __global__ __launch_bounds__(kCoopThreads) void k_fps_coop(
             naff = (int)s_n;
         }
         // update the chunks, U per wave step with 8 loads in flight per lane
-        for (int e0 = wid * U; e0 < naff; e0 += kCoopWaves * U) {
+        for (int e0 = wid * U; e0 < naff; e0 += NW * U) {
             float4 q[8];
             float mm[8];
             int64_t pp[8];
@@ -556,7 +562,6 @@ __global__ __launch_bounds__(kCoopThreads) void k_fps_coop(
             for (int c = 0; c < U; ++c) {
                 if (sl[c] < 0) continue;
                 uint64_t kb = 0;
-                float bx = 0.f, by = 0.f, bz = 0.f;
                 float mn0 = INFINITY, mn1 = INFINITY, mn2 = INFINITY, mx0 = -INFINITY, mx1 = -INFINITY, mx2 = -INFINITY;
 #pragma unroll
                 for (int u = 0; u < M; ++u) {
@@ -568,12 +573,7 @@ __global__ __launch_bounds__(kCoopThreads) void k_fps_coop(
                         mind[pp[i]] = d2;
                     }
                     const uint64_t k = fps_key(mm[i], (uint32_t)__float_as_int(q[i].w) - base_idx);
-                    if (k > kb) {
-                        kb = k;
-                        bx = q[i].x;
-                        by = q[i].y;
-                        bz = q[i].z;
-                    }
+                    kb = k > kb ? k : kb;
                     if (init) {
                         mn0 = fminf(mn0, q[i].x); mx0 = fmaxf(mx0, q[i].x);
                         mn1 = fminf(mn1, q[i].y); mx1 = fmaxf(mx1, q[i].y);
@@ -581,11 +581,6 @@ __global__ __launch_bounds__(kCoopThreads) void k_fps_coop(
                     }
                 }
                 const uint64_t km = wave_max_u64(kb);
-                const uint64_t own = __ballot(kb == km && km != 0);
-                const int src = own ? __ffsll((unsigned long long)own) - 1 : 0;
-                bx = __shfl(bx, src, 64);
-                by = __shfl(by, src, 64);
-                bz = __shfl(bz, src, 64);
                 if (init) {
 #pragma unroll
                     for (int o = 32; o > 0; o >>= 1) {
@@ -597,9 +592,6 @@ __global__ __launch_bounds__(kCoopThreads) void k_fps_coop(
                 if (lane == 0) {
                     const int s_ = sl[c];
                     s_key[s_] = km;
-                    s_px[s_] = bx;
-                    s_px[nmine + s_] = by;
-                    s_px[2 * nmine + s_] = bz;
                     if (init) {
                         s_bb[s_] = mn0; s_bb[nmine + s_] = mn1; s_bb[2 * nmine + s_] = mn2;
                         s_bb[3 * nmine + s_] = mx0; s_bb[4 * nmine + s_] = mx1; s_bb[5 * nmine + s_] = mx2;
@@ -608,66 +600,71 @@ __global__ __launch_bounds__(kCoopThreads) void k_fps_coop(
             }
         }
         __syncthreads();
-        // the workgroup's max key and the slot holding it
+        // the workgroup's max key
         uint64_t kb = 0;
-        int ks = 0;
-        for (int sl = tid; sl < nmine; sl += kCoopThreads)
-            if (s_key[sl] > kb) {
-                kb = s_key[sl];
-                ks = sl;
-            }
+        for (int sl = tid; sl < nmine; sl += NT) kb = s_key[sl] > kb ? s_key[sl] : kb;
         const uint64_t km = wave_max_u64(kb);
-        const uint64_t own = __ballot(kb == km);
-        const int src = __ffsll((unsigned long long)own) - 1;
-        ks = __shfl(ks, src, 64);
-        if (lane == 0) {
-            s_wk[wid] = km;
-            s_ws[wid] = ks;
-        }
+        if (lane == 0) s_wk[wid] = km;
         __syncthreads();
         if (wid == 0) {
             const uint32_t tag = (uint32_t)(t + 1) & 3u;
-            const int ring = t & 1;
+            uint64_t *ring = rk + (t & 1) * kMaxWG;
             if (lane == 0) {
                 uint64_t k = s_wk[0];
-                int ss = s_ws[0];
-                for (int w = 1; w < kCoopWaves; ++w)
-                    if (s_wk[w] > k) {
-                        k = s_wk[w];
-                        ss = s_ws[w];
-                    }
-                float4 pt = make_float4(0.f, 0.f, 0.f, 0.f);
-                if (nmine > 0) pt = make_float4(s_px[ss], s_px[nmine + ss], s_px[2 * nmine + ss], 0.f);
-                rp[ring * kMaxWG + wg] = pt;
-                const uint64_t rkv = nmine > 0 ? ring_key(k, tag) : ((uint64_t)tag << 30);
-                __hip_atomic_store(&rk[ring * kMaxWG + wg], rkv, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+                for (int w = 1; w < NW; ++w) k = s_wk[w] > k ? s_wk[w] : k;
+                __hip_atomic_store(&ring[wg], ring_key(k, tag), __ATOMIC_RELAXED, SCOPE);
             }
-            // poll the round's W slots
-            uint64_t best = 0;
-            int bw = 0;
+            // poll the round's W slots; each slot's point is fetched from X as
+            // soon as its key shows up, so the winner's is usually on hand
+            uint64_t v[PER];
+            float cx[PER], cy[PER], cz[PER];
+            bool have[PER];
+#pragma unroll
+            for (int i = 0; i < PER; ++i) {
+                v[i] = 0;
+                cx[i] = cy[i] = cz[i] = 0.f;
+                have[i] = lane + 64 * i >= W;
+            }
             bool done = false;
             for (int spin = 0; spin < kSpinLimit; ++spin) {
                 bool ok = true;
-                uint64_t mk = 0;
-                int mw = 0;
-                for (int w = lane; w < W; w += 64) {
-                    const uint64_t v = __hip_atomic_load(&rk[ring * kMaxWG + w], __ATOMIC_RELAXED,
-                                                         __HIP_MEMORY_SCOPE_AGENT);
-                    if ((((uint32_t)v >> 30) & 3u) != tag) ok = false;
-                    else if (v > mk) {
-                        mk = v;
-                        mw = w;
+#pragma unroll
+                for (int i = 0; i < PER; ++i) {
+                    if (have[i]) continue;
+                    const uint64_t x = __hip_atomic_load(&ring[lane + 64 * i], __ATOMIC_RELAXED, SCOPE);
+                    if ((((uint32_t)x >> 30) & 3u) == tag) {
+                        have[i] = true;
+                        v[i] = x;
+                        const int64_t row = pb + (int64_t)(0x3fffffffu - ((uint32_t)x & 0x3fffffffu));
+                        cx[i] = X[3 * row];
+                        cy[i] = X[3 * row + 1];
+                        cz[i] = X[3 * row + 2];
+                    } else {
+                        ok = false;
                     }
                 }
                 if (__all(ok)) {
-                    best = wave_max_u64(mk);
-                    const uint64_t ow = __ballot(mk == best);
-                    bw = __shfl(mw, __ffsll((unsigned long long)ow) - 1, 64);
                     done = true;
                     break;
                 }
                 __builtin_amdgcn_s_sleep(1);
             }
+            uint64_t mk = 0;
+            float bx = 0.f, by = 0.f, bz = 0.f;
+#pragma unroll
+            for (int i = 0; i < PER; ++i)
+                if (v[i] > mk) {
+                    mk = v[i];
+                    bx = cx[i];
+                    by = cy[i];
+                    bz = cz[i];
+                }
+            const uint64_t best = wave_max_u64(mk);
+            const uint64_t own = __ballot(mk == best);
+            const int src = __ffsll((unsigned long long)own) - 1;
+            bx = __shfl(bx, src, 64);
+            by = __shfl(by, src, 64);
+            bz = __shfl(bz, src, 64);
             if (lane == 0) {
                 if (!done) {
                     __hip_atomic_store(err, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -675,12 +672,9 @@ __global__ __launch_bounds__(kCoopThreads) void k_fps_coop(
                     if (wg == 0)
                         for (int tt = t + 1; tt < a.nl; ++tt) idx_out[a.lo + tt] = -1;
                 } else {
-                    // the slot's point was stored before its key was released
-                    __atomic_thread_fence(__ATOMIC_ACQUIRE);
-                    const float4 pt = rp[ring * kMaxWG + bw];
-                    s_l[0] = pt.x;
-                    s_l[1] = pt.y;
-                    s_l[2] = pt.z;
+                    s_l[0] = bx;
+                    s_l[1] = by;
+                    s_l[2] = bz;
                     if (wg == 0) {
                         if (radius) radius[a.lo + t] = sqrt_rn(__uint_as_float((uint32_t)(best >> 32)));
                         if (t + 1 < a.nl) idx_out[a.lo + t + 1] = (int32_t)(0x3fffffffu - ((uint32_t)best & 0x3fffffffu));
@@ -694,15 +688,16 @@ __global__ __launch_bounds__(kCoopThreads) void k_fps_coop(
 }
 
 template <int LM>
-static hipError_t launch_coop(const CoopArgs &a, int shmem, const float *X, const GridParam *gp, const float4 *xs,
-                              float *mind, uint64_t *rk, float4 *rp, uint32_t *err, const int64_t *start,
+static hipError_t launch_coop(const CoopArgs &a, int grid, int shmem, const float *X, const GridParam *gp,
+                              const float4 *xs, float *mind, uint64_t *rk, uint32_t *ctl, const int64_t *start,
                               int32_t *idx, float *radius, hipStream_t s) {
-    hipError_t e = hipFuncSetAttribute((const void *)k_fps_coop<LM>, hipFuncAttributeMaxDynamicSharedMemorySize, shmem);
+    hipError_t e = hipFuncSetAttribute((const void *)k_fps_coop<LM>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, shmem);
     if (e != hipSuccess) return e;
     CoopArgs aa = a;
-    void *args[] = {&aa, (void *)&X, (void *)&gp, (void *)&xs, &mind, &rk, &rp, &err, (void *)&start, &idx, &radius};
-    return hipLaunchCooperativeKernel((const void *)k_fps_coop<LM>, dim3(a.nwg), dim3(kCoopThreads), args,
-                                      (unsigned)shmem, s);
+    void *args[] = {&aa, (void *)&X, (void *)&gp, (void *)&xs, &mind, &rk, &ctl, (void *)&start, &idx, &radius};
+    return hipLaunchCooperativeKernel((const void *)k_fps_coop<LM>, dim3(grid), dim3(256),
+                                      args, (unsigned)shmem, s);
 }
 
 static int device_cus() {
@@ -712,29 +707,37 @@ static int device_cus() {
     return n;
 }
 
-// clouds below this size (and at least kCoopMin) take the cooperative path:
-// their chunk slots fit in LDS with m <= 8 on every workgroup
-static int64_t coop_limit(int cus) {
-    const int64_t wmax = std::min<int64_t>(cus, kMaxWG);
-    return std::min<int64_t>(kCoopMaxPts, wmax * kMaxCpw * 512);
-}
+struct CoopShape {
+    int32_t nwg;   // workgroups
+    int lm;
+    int64_t nchunk;
+    int shmem;
+};
 
-// workgroups W and points per lane m of a cloud's cooperative launch; false
-// if the cloud is handled by the persistent path
-static bool coop_shape(int64_t n, int cus, int32_t *nwg, int *lm, int64_t *nchunk) {
+// the cooperative launch of a cloud of n points (one workgroup per CU, at
+// least 16 chunks each); false: the persistent path
+static bool coop_shape(int64_t n, int cus, CoopShape *cs) {
     if (n < kCoopMin || n >= kCoopMaxPts || cus < 1) return false;
-    const int64_t w0 = std::min<int64_t>(std::min<int64_t>(cus, kMaxWG), std::max<int64_t>(1, (n + 64 * 16 - 1) / (64 * 16)));
+    const int64_t wmax = std::min<int64_t>(cus, kMaxWG);
     for (int l = 0; l <= 3; ++l) {
         const int64_t nc = (n + (64 << l) - 1) / (64 << l);
-        const int64_t w = std::min<int64_t>(w0, nc);
-        if ((nc + w - 1) / w <= kMaxCpw) {
-            *nwg = (int32_t)w;
-            *lm = l;
-            *nchunk = nc;
+        const int64_t w = std::min<int64_t>(wmax, std::max<int64_t>(1, nc / 16));
+        const int64_t cpw = (nc + w - 1) / w;
+        if (cpw <= kMaxCpw) {
+            cs->nwg = (int32_t)w;
+            cs->lm = l;
+            cs->nchunk = nc;
+            cs->shmem = (int)(cpw * 36);
             return true;
         }
     }
     return false;
+}
+
+// clouds below this size (and at least kCoopMin) take a cooperative path
+static int64_t coop_limit(int cus) {
+    const int64_t wmax = std::min<int64_t>(cus, kMaxWG);
+    return std::min<int64_t>(kCoopMaxPts, wmax * kMaxCpw * 512);
 }
 
 hipError_t fps_run(const float *X, int32_t B, const int64_t *x_off, const int64_t *x_off_d,
@@ -745,14 +748,13 @@ hipError_t fps_run(const float *X, int32_t B, const int64_t *x_off, const int64_
     const int64_t np = x_off[B];
     Carve c(ws, ws_bytes);
     FpsWork w;
-    grid_carve(c, B, np, tc, w.grid);
+    grid_carve(c, B, x_off, tc, w.grid);
     w.mind = c.take<float>(np);
     w.rkey = c.take<uint64_t>(tc + 1);
     w.state = c.take<FpsState>(B);
     w.l_off = c.take<int64_t>(B + 1);
     uint64_t *ring_k = c.take<uint64_t>(2 * kMaxWG);
-    float4 *ring_p = c.take<float4>(2 * kMaxWG);
-    uint32_t *err = c.take<uint32_t>(1);
+    uint32_t *ctl = c.take<uint32_t>(1);  // error flag of the cooperative launches
     if (!c.ok()) return hipErrorOutOfMemory;
     const int cus = device_cus();
     const int64_t coop_hi = coop_limit(cus);
@@ -760,7 +762,7 @@ hipError_t fps_run(const float *X, int32_t B, const int64_t *x_off, const int64_
     if (e != hipSuccess) return e;
     e = fill_f32(w.mind, INFINITY, np, s);
     if (e != hipSuccess) return e;
-    e = fill_u32(err, 0u, 1, s);
+    e = fill_u32(ctl, 0u, 1, s);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_fps_init, dim3(1), dim3(1), 0, s, B, n_lm_d, start_d, X, x_off_d, w.state, w.l_off, idx);
     // large clouds: one cooperative launch each
@@ -768,26 +770,25 @@ hipError_t fps_run(const float *X, int32_t B, const int64_t *x_off, const int64_
     int32_t rounds = 0;
     for (int32_t b = 0; b < B; ++b) {
         const int64_t n = x_off[b + 1] - x_off[b];
-        int32_t nwg = 0;
-        int lm = 0;
-        int64_t nchunk = 0;
-        if (n >= kCoopMin && n < coop_hi && coop_shape(n, cus, &nwg, &lm, &nchunk)) {
+        CoopShape cs;
+        if (n >= kCoopMin && n < coop_hi && coop_shape(n, cus, &cs)) {
             e = fill_u64(ring_k, 0ull, 2 * kMaxWG, s);
             if (e != hipSuccess) return e;
             CoopArgs a;
             a.b = b;
             a.nl = n_lm[b];
-            a.nwg = nwg;
+            a.nwg = cs.nwg;
             a.pad = 0;
-            a.nchunk = nchunk;
+            a.nchunk = cs.nchunk;
             a.lo = lo;
-            const int shmem = (int)((nchunk + nwg - 1) / nwg) * 48;
-            switch (lm) {
-                case 0: e = launch_coop<0>(a, shmem, X, w.grid.gp, w.grid.xs, w.mind, ring_k, ring_p, err, start_d, idx, radius, s); break;
-                case 1: e = launch_coop<1>(a, shmem, X, w.grid.gp, w.grid.xs, w.mind, ring_k, ring_p, err, start_d, idx, radius, s); break;
-                case 2: e = launch_coop<2>(a, shmem, X, w.grid.gp, w.grid.xs, w.mind, ring_k, ring_p, err, start_d, idx, radius, s); break;
-                default: e = launch_coop<3>(a, shmem, X, w.grid.gp, w.grid.xs, w.mind, ring_k, ring_p, err, start_d, idx, radius, s); break;
+#define FLOOD_COOP(LM_) launch_coop<LM_>(a, cs.nwg, cs.shmem, X, w.grid.gp, w.grid.xs, w.mind, ring_k, ctl, start_d, idx, radius, s)
+            switch (cs.lm) {
+                case 0: e = FLOOD_COOP(0); break;
+                case 1: e = FLOOD_COOP(1); break;
+                case 2: e = FLOOD_COOP(2); break;
+                default: e = FLOOD_COOP(3); break;
             }
+#undef FLOOD_COOP
             if (e != hipSuccess) return e;
         } else {
             nmax = n > nmax ? n : nmax;

@@ -141,6 +141,14 @@ hipError_t exclusive_scan_u32(uint32_t *data, int64_t n, uint32_t *tmp, hipStrea
 // ---------------------------------------------------------------------------
 // grid build
 
+// blocks per cloud of the bounding-box pass (each writes one partial box)
+static int bbox_blocks(int32_t B, const int64_t *x_off) {
+    int64_t nmax = 0;
+    for (int32_t b = 0; b < B; ++b) nmax = nmax > x_off[b + 1] - x_off[b] ? nmax : x_off[b + 1] - x_off[b];
+    int64_t bx = (nmax + kBlock * 8 - 1) / (kBlock * 8);
+    return (int)(bx < 1 ? 1 : (bx > 1024 ? 1024 : bx));
+}
+
 size_t grid_workspace(int32_t B, const int64_t *x_off, float alpha, int64_t *total_cells) {
     int64_t tc = 0;
     for (int32_t b = 0; b < B; ++b) tc += cells_cap(x_off[b + 1] - x_off[b], alpha);
@@ -149,6 +157,7 @@ size_t grid_workspace(int32_t B, const int64_t *x_off, float alpha, int64_t *tot
     size_t bytes = 0;
     bytes += sizeof(GridParam) * B + 256;
     bytes += sizeof(uint32_t) * 6 * B + 256;
+    bytes += sizeof(float) * 6 * (size_t)B * bbox_blocks(B, x_off) + 256;
     bytes += sizeof(float4) * np + 256;
     bytes += sizeof(uint32_t) * np + 256;
     bytes += sizeof(uint32_t) * (tc + 1) + 256;
@@ -157,9 +166,12 @@ size_t grid_workspace(int32_t B, const int64_t *x_off, float alpha, int64_t *tot
     return bytes;
 }
 
-void grid_carve(Carve &c, int32_t B, int64_t total_pts, int64_t total_cells, GridWork &g) {
+void grid_carve(Carve &c, int32_t B, const int64_t *x_off, int64_t total_cells, GridWork &g) {
+    const int64_t total_pts = x_off[B];
     g.gp = c.take<GridParam>(B);
     g.bbox = c.take<uint32_t>(6 * (size_t)B);
+    g.bbox_blocks = bbox_blocks(B, x_off);
+    g.bbox_part = c.take<float>(6 * (size_t)B * g.bbox_blocks);
     g.xs = c.take<float4>(total_pts);
     g.pcell = c.take<uint32_t>(total_pts);
     g.cell_start = c.take<uint32_t>(total_cells + 1);
@@ -169,13 +181,10 @@ void grid_carve(Carve &c, int32_t B, int64_t total_pts, int64_t total_cells, Gri
     g.total_pts = total_pts;
 }
 
-__global__ void k_bbox_init(uint32_t *bbox, int32_t B) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < 6 * B) bbox[i] = (i % 6) < 3 ? 0xffffffffu : 0u;
-}
-
-// gridDim.y = cloud; each block reduces a contiguous part of the cloud
-__global__ __launch_bounds__(kBlock) void k_bbox(const float *X, const int64_t *x_off, uint32_t *bbox) {
+// gridDim.y = cloud; block x reduces a strided share of the cloud and
+// writes its partial box (no atomics: thousands of blocks would contend on
+// six words)
+__global__ __launch_bounds__(kBlock) void k_bbox(const float *X, const int64_t *x_off, float *part) {
     const int b = blockIdx.y;
     const int64_t lo = x_off[b], hi = x_off[b + 1];
     float mn[3] = {INFINITY, INFINITY, INFINITY}, mx[3] = {-INFINITY, -INFINITY, -INFINITY};
@@ -203,19 +212,58 @@ __global__ __launch_bounds__(kBlock) void k_bbox(const float *X, const int64_t *
             s_mx[a][wid] = mx[a];
         }
     __syncthreads();
-    if (threadIdx.x == 0 && lo < hi) {
+    if (threadIdx.x == 0) {
+        float *o = part + 6 * ((int64_t)b * gridDim.x + blockIdx.x);
         for (int a = 0; a < 3; ++a) {
             float m0 = s_mn[a][0], m1 = s_mx[a][0];
             for (int w = 1; w < kBlock / 64; ++w) {
                 m0 = fminf(m0, s_mn[a][w]);
                 m1 = fmaxf(m1, s_mx[a][w]);
             }
-            if (m0 <= m1) {
-                atomicMin(&bbox[6 * b + a], float_key(m0));
-                atomicMax(&bbox[6 * b + 3 + a], float_key(m1));
-            }
+            o[a] = m0;
+            o[3 + a] = m1;
         }
     }
+}
+
+// one block per cloud: the box of the partial boxes, as ordered keys
+__global__ __launch_bounds__(kBlock) void k_bbox_final(const float *part, int nblk, uint32_t *bbox) {
+    const int b = blockIdx.x;
+    float mn[3] = {INFINITY, INFINITY, INFINITY}, mx[3] = {-INFINITY, -INFINITY, -INFINITY};
+    for (int i = threadIdx.x; i < nblk; i += blockDim.x) {
+        const float *p = part + 6 * ((int64_t)b * nblk + i);
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            mn[a] = fminf(mn[a], p[a]);
+            mx[a] = fmaxf(mx[a], p[3 + a]);
+        }
+    }
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            mn[a] = fminf(mn[a], __shfl_xor(mn[a], o, 64));
+            mx[a] = fmaxf(mx[a], __shfl_xor(mx[a], o, 64));
+        }
+    }
+    __shared__ float s_mn[3][kBlock / 64], s_mx[3][kBlock / 64];
+    const int wid = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0)
+        for (int a = 0; a < 3; ++a) {
+            s_mn[a][wid] = mn[a];
+            s_mx[a][wid] = mx[a];
+        }
+    __syncthreads();
+    if (threadIdx.x == 0)
+        for (int a = 0; a < 3; ++a) {
+            float m0 = s_mn[a][0], m1 = s_mx[a][0];
+            for (int w = 1; w < kBlock / 64; ++w) {
+                m0 = fminf(m0, s_mn[a][w]);
+                m1 = fmaxf(m1, s_mx[a][w]);
+            }
+            bbox[6 * b + a] = float_key(m0);
+            bbox[6 * b + 3 + a] = float_key(m1);
+        }
 }
 
 // one thread: grid parameters of every cloud (sequential prefix of the cell bases)
@@ -313,8 +361,8 @@ hipError_t grid_build(const float *X, int32_t B, const int64_t *x_off, const int
     int bx = (int)((nmax + kBlock * 8 - 1) / (kBlock * 8));
     if (bx < 1) bx = 1;
     if (bx > 4096) bx = 4096;
-    hipLaunchKernelGGL(k_bbox_init, dim3((6 * B + 255) / 256), dim3(256), 0, s, g.bbox, B);
-    hipLaunchKernelGGL(k_bbox, dim3(bx, B), dim3(kBlock), 0, s, X, x_off_d, g.bbox);
+    hipLaunchKernelGGL(k_bbox, dim3(g.bbox_blocks, B), dim3(kBlock), 0, s, X, x_off_d, g.bbox_part);
+    hipLaunchKernelGGL(k_bbox_final, dim3(B), dim3(kBlock), 0, s, g.bbox_part, g.bbox_blocks, g.bbox);
     hipLaunchKernelGGL(k_grid_params, dim3(1), dim3(1), 0, s, g.bbox, x_off_d, B, alpha, max_dim, morton_lo, morton_hi, g.gp);
     hipError_t e = fill_u32(g.cell_start, 0u, g.total_cells + 1, s);
     if (e != hipSuccess) return e;

@@ -77,6 +77,8 @@ __device__ inline int bin_coord(float v, float o, float inv_h, int n) {
 struct GridWork {
     GridParam *gp;        // [B]
     uint32_t *bbox;       // [B][6] ordered keys: min xyz, max xyz
+    float *bbox_part;     // [B][bbox_blocks][6] partial boxes
+    int bbox_blocks;
     float4 *xs;           // [sum N] (x, y, z, bits of global point row)
     uint32_t *pcell;      // [sum N] global cell of each point (input order)
     uint32_t *cell_start; // [total_cells + 1]
@@ -86,7 +88,7 @@ struct GridWork {
     int64_t total_pts;
 };
 size_t grid_workspace(int32_t B, const int64_t *x_off, float alpha, int64_t *total_cells);
-void grid_carve(Carve &c, int32_t B, int64_t total_pts, int64_t total_cells, GridWork &g);
+void grid_carve(Carve &c, int32_t B, const int64_t *x_off, int64_t total_cells, GridWork &g);
 hipError_t grid_build(const float *X, int32_t B, const int64_t *x_off, const int64_t *x_off_d,
                       float alpha, GridWork &g, hipStream_t s, int32_t max_dim = 1 << 20,
                       int64_t morton_lo = INT64_MAX, int64_t morton_hi = INT64_MAX);
