@@ -174,7 +174,7 @@ typedef struct {
 /* Tuning knobs; pass NULL for the defaults (a zero field also selects its
  * default).  They change speed, never the values: cells_per_point (target
  * uniform-grid cells per point, 0.05..64), samples_per_lane (1, 2 or 4),
- * waves_per_block (1..16), tile_shells (cell shells a wave scans
+ * waves_per_block (1..4), tile_shells (cell shells a wave scans
  * cooperatively around its samples before handing open samples to the
  * per-sample search, 1..8; -1 sends every sample to the per-sample search),
  * tile_extent (a tile whose samples span more cells than this along an axis

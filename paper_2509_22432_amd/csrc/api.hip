@@ -58,7 +58,7 @@ flood_status check_tuning(const flood_tuning &t) {
         return fail(FLOOD_EINVAL, "tuning: cells_per_point outside [0.05, 64]");
     if (t.samples_per_lane != 1 && t.samples_per_lane != 2 && t.samples_per_lane != 4)
         return fail(FLOOD_EINVAL, "tuning: samples_per_lane must be 1, 2 or 4");
-    if (t.waves_per_block < 1 || t.waves_per_block > 16) return fail(FLOOD_EINVAL, "tuning: waves_per_block outside [1, 16]");
+    if (t.waves_per_block < 1 || t.waves_per_block > 4) return fail(FLOOD_EINVAL, "tuning: waves_per_block outside [1, 4]");
     if (t.tile_shells < -1 || t.tile_shells > 8 || t.tile_shells == 0)
         return fail(FLOOD_EINVAL, "tuning: tile_shells must be -1 or in [1, 8]");
     if (t.tile_extent < 2 || t.tile_extent > 64) return fail(FLOOD_EINVAL, "tuning: tile_extent outside [2, 64]");

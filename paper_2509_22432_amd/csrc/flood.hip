@@ -7,15 +7,16 @@
 // of Sec. 4.1, and exactly the max over the full grid because P_tau is a
 // subset of P_sigma.
 //
-// Search (one wavefront per tile of 64*T consecutive samples; consecutive
-// simplices share their first vertex, so a tile is spatially compact):
+// Search, phase A (one wavefront per tile of 64*T samples that are
+// consecutive in Morton order, so a tile is spatially compact):
 //  * each sample starts from the bound d(p,X)^2 <= min_i |p - v_i|^2, valid
 //    when the landmarks are points of X (proof of Lemma 7);
 //  * the wave scans grid cells in growing boxes around its samples, one
-//    x-run of cells (contiguous points) at a time; a run is skipped unless
+//    x-run of cells (contiguous points) per lane; a run is kept only if
 //    some live sample's distance to the run's box is below its bound; the
-//    points of a run are read at wave-uniform addresses (scalar loads) and
-//    every live lane updates its minimum with direct-difference FP32;
+//    kept runs' points are loaded 64 at a time with one coalesced load,
+//    staged in LDS and read back at one address by every lane, which
+//    updates its minimum with direct-difference FP32;
 //  * a sample retires as soon as its bound drops below the simplex's
 //    running max M (it cannot raise f), and completes when its bound is
 //    below the distance to the unscanned region (its minimum is exact);
@@ -134,9 +135,6 @@ struct TileArgs {
     int64_t n_tiles;
 };
 
-// 0 in every lane, opaque to the compiler's uniformity analysis
-__device__ __forceinline__ uint32_t opaque_zero() { return __builtin_amdgcn_mbcnt_lo(0u, 0u); }
-
 __device__ __forceinline__ float box_lb2(float sx, float sy, float sz, float bx0, float bx1, float by0, float by1,
                                          float bz0, float bz1) {
     const float ex = fmaxf(fmaxf(bx0 - sx, sx - bx1), 0.f);
@@ -163,8 +161,12 @@ __global__ __launch_bounds__(kWaveBlock) void k_flood_tiles(
     unsigned long long *__restrict__ evals, unsigned long long *__restrict__ stats) {
     const int lane = threadIdx.x & 63;
     const int wpb = blockDim.x >> 6;
+    __shared__ float4 s_pt[kWaveBlock / 64][64];
+    __shared__ uint32_t s_p0[kWaveBlock / 64][64], s_end[kWaveBlock / 64][64];
+    float4 *sw_pt = s_pt[threadIdx.x >> 6];
+    uint32_t *sw_p0 = s_p0[threadIdx.x >> 6], *sw_end = s_end[threadIdx.x >> 6];
     // wave-uniform by construction; readfirstlane lets the compiler keep the
-    // tile state in scalar registers and load points with scalar loads
+    // tile state in scalar registers
     const int64_t wave = xcd_remap(blockIdx.x, gridDim.x) * wpb + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     if (wave >= a.n_tiles) return;
     int lo_b = 0, hi_b = a.B;
@@ -298,12 +300,11 @@ __global__ __launch_bounds__(kWaveBlock) void k_flood_tiles(
                         const float gz = fmaxf(fmaxf((g.oz + (float)z * h - eps) - lz1, lz0 - (g.oz + (float)(z + 1) * h + eps)), 0.f);
                         ok = gx * gx + gy * gy + gz * gz < bmax;
                     }
-                    uint64_t mask = __ballot(ok);
+                    // fine: keep a run only if some live sample's bound reaches its box
+                    uint64_t mask = __ballot(ok), need_m = 0;
                     while (mask) {
                         const int src = __ffsll((unsigned long long)mask) - 1;
                         mask &= mask - 1;
-                        const uint32_t q0 = __builtin_amdgcn_readlane(p0, src);
-                        const uint32_t q1 = __builtin_amdgcn_readlane(p1, src);
                         const int rx0 = __builtin_amdgcn_readlane(x0, src);
                         const int rx1 = __builtin_amdgcn_readlane(x1, src);
                         const int ry = __builtin_amdgcn_readlane(y, src);
@@ -312,21 +313,49 @@ __global__ __launch_bounds__(kWaveBlock) void k_flood_tiles(
                         const float by0 = g.oy + (float)ry * h - eps, by1 = g.oy + (float)(ry + 1) * h + eps;
                         const float bz0 = g.oz + (float)rz * h - eps, bz1 = g.oz + (float)(rz + 1) * h + eps;
                         bool need = false;
-                        int nlive = 0;
 #pragma unroll
-                        for (int t = 0; t < T; ++t) {
+                        for (int t = 0; t < T; ++t)
                             if (live[t]) need |= box_lb2(sx[t], sy[t], sz[t], bx0, bx1, by0, by1, bz0, bz1) < best[t];
-                            nlive += __popcll(__ballot(live[t]));
+                        if (__any(need)) need_m |= 1ull << src;
+                    }
+                    if (!need_m) continue;
+                    // the kept runs' points, flattened: 64 per coalesced load,
+                    // staged in LDS and read back at one address by every lane
+                    const uint32_t cnt = ((need_m >> lane) & 1ull) ? p1 - p0 : 0u;
+                    uint32_t incl = cnt;
+#pragma unroll
+                    for (int o = 1; o < 64; o <<= 1) {
+                        const uint32_t v = __shfl_up(incl, o, 64);
+                        if (lane >= o) incl += v;
+                    }
+                    const uint32_t total = __builtin_amdgcn_readlane(incl, 63);
+                    sw_p0[lane] = p0;
+                    sw_end[lane] = incl;
+                    int nlive = 0;
+#pragma unroll
+                    for (int t = 0; t < T; ++t) nlive += __popcll(__ballot(live[t]));
+                    nev += (unsigned long long)total * (unsigned long long)nlive;
+                    __builtin_amdgcn_wave_barrier();
+                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                    for (uint32_t b0 = 0; b0 < total; b0 += 64) {
+                        const uint32_t k = b0 + (uint32_t)lane;
+                        float4 c = make_float4(INFINITY, INFINITY, INFINITY, 0.f);
+                        if (k < total) {
+                            int rr = 0, hi_r = 63;  // first run whose inclusive end exceeds k
+                            while (rr < hi_r) {
+                                const int mid = (rr + hi_r) >> 1;
+                                if (sw_end[mid] > k) hi_r = mid;
+                                else rr = mid + 1;
+                            }
+                            c = xs[sw_p0[rr] + (k - (rr ? sw_end[rr - 1] : 0u))];
                         }
-                        if (!__any(need)) continue;
-                        nev += (unsigned long long)(q1 - q0) * (unsigned long long)nlive;
-                        // wave-uniform addresses, but issued as vector loads:
-                        // the scalar data cache is not kept coherent with the
-                        // scatter that rewrote xs earlier in this call
-                        const float4 *xv = xs + opaque_zero();
-                        uint32_t p = q0;
-                        for (; p + 3 < q1; p += 4) {
-                            const float4 c0 = xv[p], c1 = xv[p + 1], c2 = xv[p + 2], c3 = xv[p + 3];
+                        __builtin_amdgcn_wave_barrier();
+                        sw_pt[lane] = c;
+                        __builtin_amdgcn_wave_barrier();
+                        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                        const int n4 = (int)((min(total - b0, 64u) + 3u) & ~3u);
+                        for (int j = 0; j < n4; j += 4) {
+                            const float4 c0 = sw_pt[j], c1 = sw_pt[j + 1], c2 = sw_pt[j + 2], c3 = sw_pt[j + 3];
 #pragma unroll
                             for (int t = 0; t < T; ++t) {
                                 const float d0 = dist2(sx[t], sy[t], sz[t], c0.x, c0.y, c0.z);
@@ -336,12 +365,7 @@ __global__ __launch_bounds__(kWaveBlock) void k_flood_tiles(
                                 best[t] = fminf(fminf(best[t], fminf(d0, d1)), fminf(d2, d3));
                             }
                         }
-                        for (; p < q1; ++p) {
-                            const float4 c0 = xv[p];
-#pragma unroll
-                            for (int t = 0; t < T; ++t)
-                                best[t] = fminf(best[t], dist2(sx[t], sy[t], sz[t], c0.x, c0.y, c0.z));
-                        }
+                        __builtin_amdgcn_wave_barrier();
                     }
                 }
             }
@@ -407,10 +431,12 @@ __global__ __launch_bounds__(kWaveBlock) void k_flood_tiles(
 // ---------------------------------------------------------------------------
 // phase B: one wavefront per open sample.  The lanes take the rows (y,z) of
 // the grid in Chebyshev rings around the sample's cell, 64 rows per round
-// trip; each lane scans the x-range of its row that can beat the current
-// bound and keeps the lexicographic minimum (d^2, point row); a wave
-// reduction after every chunk shares the bound.  Ring r cannot hold a point
-// closer than (r-1) h, which ends the search.
+// trip; each row contributes the x-range that can beat the current bound,
+// the rows' points are flattened over the lanes and every lane keeps the
+// lexicographic minimum (d^2, point row); a wave reduction after every step
+// shares the bound.  (Wider steps scan more points: the rows of one step
+// share the bound from its start.)  Ring r cannot hold a point closer than
+// (r-1) h, which ends the search.
 
 struct DeepArgs {
     int32_t d, k, n_int, B;
@@ -447,6 +473,7 @@ __device__ __forceinline__ void lex_min(float &bd, int32_t &bi, float od, int32_
 // (squared distance, point row) over all points with distance^2 <= the
 // initial bd, unless `retire` is set and the bound fell below M (then the
 // function returns true early and (bd, bi) is only an upper bound).
+// s_p0 / s_end: 64 entries of LDS per wave.
 __device__ bool ring_search(const GridParam &g, const uint32_t *__restrict__ cs, const float4 *__restrict__ xs,
                             float sx, float sy, float sz, float &bd, int32_t &bi, bool retire, float &M,
                             const uint64_t *__restrict__ keyj, uint32_t *s_p0, uint32_t *s_end, int lane,
@@ -455,7 +482,7 @@ __device__ bool ring_search(const GridParam &g, const uint32_t *__restrict__ cs,
     const int cy = cell_of(sy, g.oy, g.inv_h, g.ny), cz = cell_of(sz, g.oz, g.inv_h, g.nz);
     const int rmax = max(max(cy, g.ny - 1 - cy), max(cz, g.nz - 1 - cz));
     const float h = g.h, eps = g.eps;
-    for (int base = 0;; base += 64) {
+    for (int base = 0; ; base += 64) {
         int r0, dy0, dz0;
         ring_pos(base, r0, dy0, dz0);
         if (r0 > rmax) break;

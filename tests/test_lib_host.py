@@ -62,6 +62,12 @@ def test_filtration_rejects_small_workspace_and_bad_tuning():
     assert L.flood_filtration(ctypes.byref(pb), ctypes.byref(t), ctypes.byref(out), None, 0, None) == _lib.EINVAL
     t = _lib.Tuning(1.0, 3, 4, 0, 0)
     assert L.flood_filtration(ctypes.byref(pb), ctypes.byref(t), ctypes.byref(out), None, 0, None) == _lib.EINVAL
+    # the tile kernel runs at most four waves per block
+    t = _lib.Tuning(1.0, 1, 5, 0, 0)
+    assert L.flood_filtration(ctypes.byref(pb), ctypes.byref(t), ctypes.byref(out), None, 0, None) == _lib.EINVAL
+    for bad in ((1.0, 1, 4, 9, 0), (1.0, 1, 4, 0, 65), (1.0, 1, 4, 0, 1)):
+        t = _lib.Tuning(*bad)
+        assert L.flood_filtration(ctypes.byref(pb), ctypes.byref(t), ctypes.byref(out), None, 0, None) == _lib.EINVAL
 
 
 def test_fps_rejects_bad_arguments():
