@@ -50,6 +50,25 @@ class HipEvents:
         return ms.value
 
 
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed counter summary
+    (FETCH_SIZE and WRITE_SIZE passes scaled by a plain-copy calibration),
+    or None when the kernel's sources changed since the counters were taken."""
+    import hashlib
+    try:
+        t = json.load(open(os.path.join(ROOT, "profiles", "traffic.json")))
+        k = t["kernels"][kernel]
+    except (OSError, KeyError, ValueError):
+        return None
+    srcs = {"flood::k_fps_coop<0>": ["fps.hip", "internal.hpp"]}.get(kernel, ["flood.hip", "sample.hpp", "internal.hpp"])
+    m = hashlib.sha256()
+    for f in srcs:
+        m.update(open(os.path.join(ROOT, "paper_2509_22432_amd", "csrc", f), "rb").read())
+    if m.hexdigest() != k["sources_sha256"]:
+        return None
+    return k["fetch_bytes_per_launch"] + k["write_bytes_per_launch"]
+
+
 def cpu_baseline(X, Lxyz, cx, k, budget_s):
     """The oracle (masked FP64 mode) on a bounded random sample of the same
     simplices; returns its distance evaluations per second."""
@@ -174,7 +193,7 @@ def main():
     b_ms = float(np.mean([sum(t[d][1] for d in range(4)) for t in tile_ms]))
     st = np.mean(stats_steps, axis=0)
     a_ev, b_ev = float(st[:, 2].sum()), float(st[:, 3].sum())
-    dominant = ("k_flood_deep", b_ev, b_ms) if b_ms >= a_ms else ("k_flood_tiles", a_ev, a_ms)
+    dominant = ("k_flood_deep", b_ev, b_ms) if b_ms >= a_ms else ("k_flood_tiles<1>", a_ev, a_ms)
     achieved = FLOP_PER_EVAL * dominant[1] / (dominant[2] * 1e-3) / 1e12
     nsimp = V + E + F + T
     out = {
@@ -206,11 +225,23 @@ def main():
                      "per_sample_search_per_dim": [float(np.mean([t[d][1] for t in tile_ms])) for d in range(4)],
                      "delaunay_host_once": del_ms},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / FP32_PEAK_TFLOPS, "traffic": None,
+                     "frac": achieved / FP32_PEAK_TFLOPS, "traffic": measured_traffic("flood::" + dominant[0]),
+                     "traffic_unit": "bytes per launch (HBM, rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+                     "launches_per_step": 4,
                      "kernel": dominant[0], "kernel_ms_per_step": dominant[2], "flop_per_eval": FLOP_PER_EVAL,
                      "other_search_kernel": {"k_flood_tiles": {"ms": a_ms, "evals": a_ev},
                                              "k_flood_deep": {"ms": b_ms, "evals": b_ev}}},
     }
+    # the persistence step after the flooding (host), outside the timed step
+    fh = [run.f[d].detach().cpu().numpy() for d in range(4)]
+    ph_ms = []
+    for _ in range(3):
+        t0 = time.time()
+        dg = P.persistence(cx, fh)
+        ph_ms.append((time.time() - t0) * 1e3)
+    out["persistence"] = {"host_ms": float(np.median(ph_ms)), "simplices": nsimp,
+                          "diagram_points_per_dim": [int(len(dg[p]["birth"])) for p in range(3)],
+                          "essential_per_dim": [int(np.isinf(dg[p]["death"]).sum()) for p in range(3)]}
     if not args.no_cpu_baseline:
         print("bench: cpu baseline (oracle) ...", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(X, Lxyz, cx, args.k, args.cpu_seconds)

@@ -112,6 +112,40 @@ flood_status flood_complex_export(const flood_complex *cx, int32_t *edges, int32
 void flood_complex_free(flood_complex *cx);
 
 /* ---------------------------------------------------------------------------
+ * Persistence diagrams of a flood filtration over Z/2, dimensions 0..2, on
+ * the host: the homology step that follows the flooding (the paper computes
+ * it with Gudhi; Sec. 2 defines the sublevel filtration and the diagrams).
+ * Simplices are ordered by (f, dimension, vertex tuple) and the boundary
+ * matrix is reduced column by column with the clearing shortcut.
+ *
+ *   n[0..3]    simplices per dimension (vertices, edges, triangles, tets)
+ *   edges      host int32 [n1][2] vertex rows; tri_edges [n2][3] and
+ *              tet_tris [n3][4] facet rows, facet i omitting the row's
+ *              i-th vertex -- exactly as flood_complex_export writes them.
+ *              Rows of each dimension must be in lexicographic order of
+ *              their sorted vertex tuples (ties in f are broken by it).
+ *   f[d]       host float [n[d]] flood values with f(face) <= f(coface)
+ *   out        receives a library-owned diagram; free with flood_diagram_free
+ * EINVAL: NULL arguments, NaN, a face index out of range, or a face whose
+ * value exceeds its coface's.  The diagram keeps pairs of positive
+ * persistence and the essential classes (death = +inf).
+ */
+typedef struct flood_diagram flood_diagram;
+flood_status flood_persistence(const int64_t n[4], const int32_t *edges, const int32_t *tri_edges,
+                               const int32_t *tet_tris, const float *const f[4], flood_diagram **out);
+/* counts[p] = points of the dimension-p diagram (finite pairs + essential). */
+flood_status flood_diagram_counts(const flood_diagram *dg, int64_t counts[3]);
+/* Copies the dimension-p points into caller-owned host arrays of
+ * counts[p] entries: births, deaths (+inf for essential classes), and the
+ * row of the birth simplex (dimension p) and of the death simplex
+ * (dimension p+1; -1 if essential).  Finite pairs come in the filtration
+ * order of their birth simplex, then the essential classes.  Any output
+ * pointer may be NULL. */
+flood_status flood_diagram_export(const flood_diagram *dg, int32_t dim, float *birth, float *death,
+                                  int64_t *birth_row, int64_t *death_row);
+void flood_diagram_free(flood_diagram *dg);
+
+/* ---------------------------------------------------------------------------
  * Flood filtration (equation (1) above), B clouds at once.
  *
  * Cloud b owns points X[x_off[b]..x_off[b+1]), landmarks

@@ -67,6 +67,14 @@ def lib():
     L.flood_filtration.argtypes = [P(Problem), P(Tuning), P(Outputs), c_vp, c_sz, c_vp]
     L.flood_filtration_backward.restype = c_i32
     L.flood_filtration_backward.argtypes = [P(Problem), P(Outputs), c_vp * 4, c_vp, c_vp, c_vp]
+    L.flood_persistence.restype = c_i32
+    L.flood_persistence.argtypes = [P(c_i64), c_vp, c_vp, c_vp, c_vp * 4, P(c_vp)]
+    L.flood_diagram_counts.restype = c_i32
+    L.flood_diagram_counts.argtypes = [c_vp, P(c_i64)]
+    L.flood_diagram_export.restype = c_i32
+    L.flood_diagram_export.argtypes = [c_vp, c_i32, c_vp, c_vp, c_vp, c_vp]
+    L.flood_diagram_free.restype = None
+    L.flood_diagram_free.argtypes = [c_vp]
     _lib = L
     return L
 
@@ -78,4 +86,5 @@ def check(status):
 
 EXPORTED = ["flood_last_error", "flood_fps_workspace_size", "flood_fps", "flood_delaunay",
             "flood_complex_counts", "flood_complex_export", "flood_complex_free",
-            "flood_filtration_workspace_size", "flood_filtration", "flood_filtration_backward"]
+            "flood_filtration_workspace_size", "flood_filtration", "flood_filtration_backward",
+            "flood_persistence", "flood_diagram_counts", "flood_diagram_export", "flood_diagram_free"]

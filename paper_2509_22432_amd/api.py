@@ -112,6 +112,40 @@ def delaunay(Lxyz) -> Complex:
     return Complex(P.shape[0], E, F, T, te, tt, int(cnt[4]))
 
 
+def persistence(cx: Complex, f):
+    """Persistence diagrams of the flood filtration f = (f0, f1, f2, f3) on cx
+    (host library call; arrays are copied to the host).  Returns
+    {p: dict(birth, death, birth_row, death_row)} for p = 0, 1, 2; essential
+    classes have death = +inf and death_row = -1."""
+    fh = [np.ascontiguousarray(np.asarray(v.detach().cpu() if torch.is_tensor(v) else v, dtype=np.float32))
+          for v in f]
+    n = (ctypes.c_int64 * 4)(*[int(x) for x in cx.counts()])
+    for d in range(4):
+        if fh[d].shape != (n[d],):
+            raise ValueError("f[%d] must have %d entries" % (d, n[d]))
+    vp = lambda a: a.ctypes.data_as(ctypes.c_void_p)
+    E = np.ascontiguousarray(cx.E, dtype=np.int32)
+    te = np.ascontiguousarray(cx.tri_edges, dtype=np.int32)
+    tt = np.ascontiguousarray(cx.tet_tris, dtype=np.int32)
+    fp = (ctypes.c_void_p * 4)(*[vp(a) for a in fh])
+    L = lib()
+    h = ctypes.c_void_p()
+    check(L.flood_persistence(n, vp(E), vp(te), vp(tt), fp, ctypes.byref(h)))
+    try:
+        cnt = (ctypes.c_int64 * 3)()
+        check(L.flood_diagram_counts(h, cnt))
+        out = {}
+        for p in range(3):
+            m = int(cnt[p])
+            b, dth = np.zeros(m, np.float32), np.zeros(m, np.float32)
+            br, dr = np.zeros(m, np.int64), np.zeros(m, np.int64)
+            check(L.flood_diagram_export(h, p, vp(b), vp(dth), vp(br), vp(dr)))
+            out[p] = dict(birth=b, death=dth, birth_row=br, death_row=dr)
+    finally:
+        L.flood_diagram_free(h)
+    return out
+
+
 # ---------------------------------------------------------------------------
 # flooding
 

@@ -10,7 +10,7 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libflood.so")
 
 HIP_SOURCES = ["grid.hip", "fps.hip", "flood.hip", "backward.hip", "api.hip"]
-CXX_SOURCES = ["delaunay.cpp"]  # host only
+CXX_SOURCES = ["delaunay.cpp", "persistence.cpp"]  # host only
 ARCH = os.environ.get("FLOOD_OFFLOAD_ARCH", "gfx950")
 
 # Packed FP32 instructions are disabled (-packed-fp32-ops): some of their

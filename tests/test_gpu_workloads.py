@@ -32,6 +32,16 @@ def test_persistence_diagrams_match():
         # near-zero persistence pairs may appear on one side only: the
         # matching lets them go to the diagonal within tol
         assert OPH.bottleneck_leq(dg_ref[p], dg_gpu[p], tol)
+    # the library's persistence step on the GPU values: the same diagrams as
+    # the oracle's reduction on those values, exactly
+    lib_dg = P.persistence(res["cx"], [res["out"]["f"][d] for d in range(4)])
+    for p in range(3):
+        fin = np.isfinite(lib_dg[p]["death"])
+        got = np.stack([lib_dg[p]["birth"][fin], lib_dg[p]["death"][fin]], 1).astype(np.float64)
+        want = dg_gpu[p][0].reshape(-1, 2)
+        srt = lambda a: a[np.lexsort((a[:, 1], a[:, 0]))]
+        assert np.array_equal(srt(got), srt(want)), p
+        assert np.array_equal(np.sort(lib_dg[p]["birth"][~fin].astype(np.float64)), np.sort(dg_gpu[p][1])), p
 
 
 def test_batched_clouds_fp32_vs_fp64_per_dim():
