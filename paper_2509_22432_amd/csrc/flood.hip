@@ -574,7 +574,8 @@ __device__ __forceinline__ int find_cloud(const int64_t *__restrict__ s_off, int
     return lo_b;
 }
 
-static constexpr uint32_t kGrab = 4;  // queue entries a wave takes per atomic
+static constexpr uint32_t kGrab = 4;    // queue entries a wave takes per atomic
+static constexpr uint32_t kSeg = 128;   // queue segment of one XCD (a few tiles' open samples)
 
 __global__ __launch_bounds__(kWaveBlock) void k_flood_deep(
     DeepArgs a, const float *__restrict__ L, const int32_t *__restrict__ simp, const int64_t *__restrict__ s_off,
@@ -587,12 +588,18 @@ __global__ __launch_bounds__(kWaveBlock) void k_flood_deep(
     const uint32_t n = *queue_count;
     if (stats && blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(&stats[4 * a.d + 1], (unsigned long long)n);
     unsigned long long nev = 0;
+    // workgroups are dispatched to the 8 XCDs round-robin; each XCD takes the
+    // queue segments x, x+8, ... through its own counter, so neighbouring
+    // samples (same tile, same grid rows) meet in one L2
+    const uint32_t xcd = blockIdx.x & 7u;
     while (true) {
-        uint32_t i0 = 0;
-        if (lane == 0) i0 = atomicAdd(queue_next, kGrab);
-        i0 = __builtin_amdgcn_readfirstlane(i0);
-        if (i0 >= n) break;
-        for (uint32_t i = i0; i < min(n, i0 + kGrab); ++i) {
+        uint32_t v0 = 0;
+        if (lane == 0) v0 = atomicAdd(&queue_next[xcd], kGrab);
+        v0 = __builtin_amdgcn_readfirstlane(v0);
+        if (((v0 / kSeg) * 8u + xcd) * kSeg + v0 % kSeg >= n) break;
+        for (uint32_t vq = v0; vq < v0 + kGrab; ++vq) {
+            const uint32_t i = ((vq / kSeg) * 8u + xcd) * kSeg + vq % kSeg;  // increases with vq
+            if (i >= n) break;
             const uint64_t e = queue[i];
             const uint32_t gid = (uint32_t)(e >> 32);
             float bd = __uint_as_float((uint32_t)e);
@@ -627,7 +634,7 @@ __global__ __launch_bounds__(kWaveBlock) void k_winner_search(
     const uint32_t *__restrict__ cs, const float4 *__restrict__ xs, int32_t *__restrict__ win_x) {
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     __shared__ uint32_t s_p0[kWaveBlock / 64][64], s_end[kWaveBlock / 64][64];
-    const int64_t j = (int64_t)blockIdx.x * (blockDim.x >> 6) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int64_t j = xcd_remap(blockIdx.x, gridDim.x) * (blockDim.x >> 6) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     if (j >= n) return;
     const uint64_t kv = key[j];
     if (kv == 0) return;
@@ -727,7 +734,7 @@ size_t flood_workspace(const flood_problem *pb, float alpha, FloodSizes *sz) {
     bytes += 2 * (sizeof(uint32_t) * (bkmax + 1) + 256); // bucket counts and cursors
     bytes += sizeof(uint32_t) * scan_tmp_elems(bkmax + 1) + 256;
     bytes += sizeof(int32_t) * (pb->B + 1) + sizeof(uint32_t) * (pb->B + 1) + 512;
-    bytes += sizeof(uint32_t) * 8 + 256;              // queue counters
+    bytes += sizeof(uint32_t) * 16 + 256;             // queue count and per-XCD cursors
     bytes += 4 * (sizeof(int64_t) * (pb->B + 1) + 256); // tile offsets
     bytes += 1024;
     if (sz) {
@@ -766,7 +773,7 @@ hipError_t flood_run(const flood_problem *pb, const flood_tuning &tu, const floo
     float *seed = c.take<float>(nmax + 1);
     uint64_t *key = c.take<uint64_t>(nmax + 1);
     uint64_t *hard = c.take<uint64_t>(smax + 1);
-    uint32_t *counters = c.take<uint32_t>(8);
+    uint32_t *counters = c.take<uint32_t>(16);  // [0] open samples, [8..15] per-XCD queue cursors
     int64_t bkmax = 0;
     for (int d = 0; d < 4; ++d) {
         int64_t bk = 0;
@@ -800,7 +807,7 @@ hipError_t flood_run(const flood_problem *pb, const flood_tuning &tu, const floo
                            pb->tri_edges, pb->tet_tris, d > 0 ? out->f[d - 1] : nullptr, seed);
         e = fill_u64(key, 0ull, n, s);
         if (e != hipSuccess) return e;
-        e = fill_u32(counters, 0u, 8, s);
+        e = fill_u32(counters, 0u, 16, s);
         if (e != hipSuccess) return e;
         if (nint > 0) {
             const int64_t tsamp = 64 * (int64_t)T;
@@ -850,7 +857,7 @@ hipError_t flood_run(const flood_problem *pb, const flood_tuning &tu, const floo
                 da.n_int = (int32_t)nint;
                 da.B = pb->B;
                 hipLaunchKernelGGL(k_flood_deep, dim3(2048), dim3(256), 0, s, da, pb->Lxyz, simp, soff_d, seed, key,
-                                   g.gp, g.cell_start, g.xs, hard, counters, counters + 1,
+                                   g.gp, g.cell_start, g.xs, hard, counters, counters + 8,
                                    (unsigned long long *)out->evals, (unsigned long long *)out->stats);
                 if (out->tile_events[3 * d + 2]) {
                     e = hipEventRecord((hipEvent_t)out->tile_events[3 * d + 2], s);
