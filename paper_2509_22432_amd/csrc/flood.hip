@@ -575,7 +575,7 @@ __device__ __forceinline__ int find_cloud(const int64_t *__restrict__ s_off, int
 }
 
 static constexpr uint32_t kGrab = 4;    // queue entries a wave takes per atomic
-static constexpr uint32_t kSeg = 128;   // queue segment of one XCD (a few tiles' open samples)
+static constexpr uint32_t kSeg = 2048;  // queue segment of one XCD (spatially adjacent open samples)
 
 __global__ __launch_bounds__(kWaveBlock) void k_flood_deep(
     DeepArgs a, const float *__restrict__ L, const int32_t *__restrict__ simp, const int64_t *__restrict__ s_off,
