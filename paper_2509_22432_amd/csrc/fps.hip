@@ -31,7 +31,9 @@ static constexpr int kDenseBlock = 256;
 static constexpr int kPT = 1024;       // persistent workgroup
 static constexpr int kU = 8;           // points per thread per step
 static constexpr int kMaxDim = 1024;   // cells per axis of a row grid (slab keys fit in LDS)
-static constexpr int kMaxWG = 256;     // workgroups of one cooperative launch (ring slots per round)
+static constexpr int kMaxWG = 256;     // workgroups of one cooperative launch
+static constexpr int kRec = 32;        // 64-bit words of a workgroup's record in an exchange
+static constexpr int kDec = 48;        // 64-bit words of an exchange's decision
 
 struct FpsState {
     int32_t cur;  // local index of the newest landmark
@@ -59,7 +61,7 @@ size_t fps_workspace(int32_t B, const int64_t *x_off, const int32_t *n_lm) {
     bytes += sizeof(uint64_t) * (tc + 1) + 256;
     bytes += sizeof(FpsState) * B + 256;
     bytes += sizeof(int64_t) * (B + 1) + 256;
-    bytes += sizeof(uint64_t) * 2 * kMaxWG + 256;  // cooperative ring
+    bytes += sizeof(uint64_t) * 2 * ((size_t)kMaxWG * kRec + kDec) + 512;  // cooperative exchange records and decisions
     bytes += sizeof(uint32_t) + 256;
     return bytes + 1024;
 }
@@ -433,16 +435,38 @@ __global__ __launch_bounds__(kPT) void k_fps_persist(
 
 // ---------------------------------------------------------------------------
 // cooperative rounds (large clouds)
+//
+// One launch per cloud; chunk c of 64*m Morton-consecutive points belongs
+// to workgroup c mod W, which keeps per chunk in LDS: the bounding box, the
+// best key (running minimum bits << 32 | ~index) with its point, and the
+// second-largest running minimum.  The landmarks are decided in exchanges
+// of up to kJ at a time:
+//  1. every workgroup applies the landmarks of the previous exchange to
+//     the chunks they can lower (box closer than the chunk's best minimum)
+//     and publishes its kK best chunks (best point, its coordinates, the
+//     chunk's second minimum and box) and the key of its next chunk;
+//  2. workgroup 0 collects the W records and replays the greedy rule on
+//     them: the next landmark is the best published candidate after the
+//     landmarks picked so far, accepted only while its key exceeds every
+//     bound on the unpublished points -- the next chunk's key, and per
+//     published chunk min(second minimum, farthest box corner from each
+//     pick); the first pick is always exact (it is the global maximum);
+//  3. it publishes the picks and every workgroup reads them.
+// So the picks are exactly those of the one-at-a-time greedy rule, and a
+// chunk update and two exchanges through memory are shared by several
+// landmarks.  Exchanged words carry the exchange number, so a stale word is
+// never taken for a fresh one.
 
-static constexpr int kMaxCpw = 4096;              // chunk slots per workgroup (36 B of LDS each)
+static constexpr int kMaxCpw = 2816;              // chunk slots per workgroup (52 B of LDS each)
 static constexpr int64_t kCoopMin = 1 << 19;      // clouds of at least this many points
-static constexpr int64_t kCoopMaxPts = 1 << 30;   // the ring key keeps 30 index bits
-static constexpr int kSpinLimit = 1 << 22;        // polls of one round before the launch gives up
+static constexpr int kSpinLimit = 1 << 22;        // polls of one exchange before the launch gives up
+static constexpr int kK = 2;                      // candidates a workgroup publishes
+static constexpr int kJ = 8;                      // landmarks decided per exchange, at most
 
 struct CoopArgs {
     int32_t b;       // cloud
     int32_t nl;      // landmarks
-    int32_t nwg;     // working workgroups W
+    int32_t nwg;     // workgroups W
     int32_t pad;
     int64_t nchunk;  // chunks of 64*m points
     int64_t lo;      // first landmark slot of the cloud in idx/radius
@@ -457,34 +481,63 @@ __device__ __forceinline__ float fps_box_d2(float lx, float ly, float lz, const 
     return __fadd_rn(__fadd_rn(__fmul_rn(dx, dx), __fmul_rn(dy, dy)), __fmul_rn(dz, dz));
 }
 
-// ring key: minimum bits << 32 | tag << 30 | (2^30 - 1 - index); the 2-bit
-// tag (round + 1) mod 4 tells a slot written this round from one written
-// two rounds ago or cleared before the launch
-__device__ __forceinline__ uint64_t ring_key(uint64_t k, uint32_t tag) {
-    const uint32_t idx = 0xffffffffu - (uint32_t)k;
-    return (k & 0xffffffff00000000ull) | ((uint64_t)tag << 30) | (uint64_t)(0x3fffffffu - idx);
+// upper bound of fps_d2 over a box: per axis the larger rounded difference
+// to the two faces (fl(p - l) is monotone in p)
+__device__ __forceinline__ float fps_box_far_d2(float lx, float ly, float lz, const float *bb) {
+    const float dx = fmaxf(fabsf(__fsub_rn(bb[0], lx)), fabsf(__fsub_rn(bb[3], lx)));
+    const float dy = fmaxf(fabsf(__fsub_rn(bb[1], ly)), fabsf(__fsub_rn(bb[4], ly)));
+    const float dz = fmaxf(fabsf(__fsub_rn(bb[2], lz)), fabsf(__fsub_rn(bb[5], lz)));
+    return __fadd_rn(__fadd_rn(__fmul_rn(dx, dx), __fmul_rn(dy, dy)), __fmul_rn(dz, dz));
 }
 
-// LM = log2(m) points per lane per chunk.  Keys cross workgroups through
-// memory (agent-scope atomics: each XCD has its own L2); a stale slot never
-// carries the round's tag, so it only delays the poll.
-// LDS per chunk slot: max key, box (6 floats), list entry.
+// an exchanged word: 32-bit payload, 32-bit exchange number
+__device__ __forceinline__ uint64_t xw(uint32_t payload, uint32_t id) { return ((uint64_t)payload << 32) | id; }
+__device__ __forceinline__ uint32_t xw_val(uint64_t w) { return (uint32_t)(w >> 32); }
+__device__ __forceinline__ bool xw_ok(uint64_t w, uint32_t id) { return (uint32_t)w == id; }
+
+// the largest key a point of running minimum m can carry (any index)
+__device__ __forceinline__ uint64_t key_bound(float m) { return ((uint64_t)__float_as_uint(m) << 32) | 0xffffffffull; }
+
+// keep the three largest (key, slot) pairs
+__device__ __forceinline__ void top3_insert(uint64_t (&k)[3], int (&s)[3], uint64_t v, int sv) {
+    if (v > k[2]) {
+        if (v > k[1]) {
+            k[2] = k[1];
+            s[2] = s[1];
+            if (v > k[0]) {
+                k[1] = k[0];
+                s[1] = s[0];
+                k[0] = v;
+                s[0] = sv;
+            } else {
+                k[1] = v;
+                s[1] = sv;
+            }
+        } else {
+            k[2] = v;
+            s[2] = sv;
+        }
+    }
+}
+
 template <int LM>
 __global__ __launch_bounds__(256) void k_fps_coop(
     CoopArgs a, const float *__restrict__ X, const GridParam *__restrict__ gp, const float4 *__restrict__ xs,
-    float *__restrict__ mind, uint64_t *__restrict__ rk, uint32_t *__restrict__ ctl,
+    float *__restrict__ mind, uint64_t *__restrict__ rec, uint64_t *__restrict__ dec, uint32_t *__restrict__ ctl,
     const int64_t *__restrict__ start, int32_t *__restrict__ idx_out, float *__restrict__ radius) {
     constexpr int NT = 256;
     constexpr int NW = NT / 64;
-    constexpr int M = 1 << LM;     // points per lane per chunk
-    constexpr int U = 8 >> LM;     // chunks per wave step
-    constexpr int PER = kMaxWG / 64;  // ring slots polled per lane
+    constexpr int M = 1 << LM;          // points per lane per chunk
+    constexpr int U = 8 >> LM;          // chunks per wave step
+    constexpr int PER = kMaxWG / 64;    // workgroup records a lane of the leader reads
     constexpr int SCOPE = __HIP_MEMORY_SCOPE_AGENT;
+    static_assert(1 + 12 * kK <= kRec && 1 + 5 * kJ <= kDec && 1 + 5 * kJ <= 64, "exchange layout");
     extern __shared__ __align__(16) unsigned char smem[];
-    __shared__ float s_l[4];
+    __shared__ float s_pk[kJ][3];       // landmarks to apply
+    __shared__ int s_np, s_j, s_abort;
     __shared__ uint32_t s_n;
-    __shared__ int s_abort;
-    __shared__ uint64_t s_wk[NW];
+    __shared__ uint64_t s_tk[NW][3];
+    __shared__ int s_ts[NW][3];
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     const int W = a.nwg;
     const int wg = blockIdx.x;
@@ -492,24 +545,35 @@ __global__ __launch_bounds__(256) void k_fps_coop(
     const int nmine = (int)((a.nchunk - wg + W - 1) / W);  // chunk slots owned (W <= nchunk)
     uint64_t *s_key = (uint64_t *)smem;
     float *s_bb = (float *)(s_key + nmine);
-    uint32_t *s_list = (uint32_t *)(s_bb + 6 * nmine);
+    float *s_px = s_bb + 6 * nmine;
+    float *s_sec = s_px + 3 * nmine;
+    uint32_t *s_list = (uint32_t *)(s_sec + nmine);
 
     const GridParam g = gp[a.b];
     const int64_t pb = g.pt_base, npts = g.npts;
     const uint32_t base_idx = (uint32_t)pb;
     if (tid == 0) {
         const int64_t row = pb + (start ? start[a.b] : 0);
-        s_l[0] = X[3 * row];
-        s_l[1] = X[3 * row + 1];
-        s_l[2] = X[3 * row + 2];
+        s_pk[0][0] = X[3 * row];
+        s_pk[0][1] = X[3 * row + 1];
+        s_pk[0][2] = X[3 * row + 2];
+        s_np = 1;
         s_abort = 0;
     }
     __syncthreads();
 
-    for (int t = 0; t < a.nl; ++t) {
-        const float lx = s_l[0], ly = s_l[1], lz = s_l[2];
-        const bool init = t == 0;
-        // chunks the landmark can lower (all of them in round 0)
+    int t_done = 1;  // landmark slots decided (slot 0 is the start point)
+    for (uint32_t e = 0;; ++e) {
+        const bool init = e == 0;
+        const int np = s_np;
+        float lk[kJ][3];
+#pragma unroll
+        for (int i = 0; i < kJ; ++i) {
+            lk[i][0] = i < np ? s_pk[i][0] : 0.f;
+            lk[i][1] = i < np ? s_pk[i][1] : 0.f;
+            lk[i][2] = i < np ? s_pk[i][2] : 0.f;
+        }
+        // 1. the chunks some landmark can lower (all of them at first)
         int naff;
         if (init) {
             naff = nmine;
@@ -522,7 +586,10 @@ __global__ __launch_bounds__(256) void k_fps_coop(
                 if (sl < nmine) {
                     const float bb[6] = {s_bb[sl], s_bb[nmine + sl], s_bb[2 * nmine + sl],
                                          s_bb[3 * nmine + sl], s_bb[4 * nmine + sl], s_bb[5 * nmine + sl]};
-                    hit = fps_box_d2(lx, ly, lz, bb) < __uint_as_float((uint32_t)(s_key[sl] >> 32));
+                    const float km = __uint_as_float((uint32_t)(s_key[sl] >> 32));
+#pragma unroll
+                    for (int i = 0; i < kJ; ++i)
+                        if (i < np) hit |= fps_box_d2(lk[i][0], lk[i][1], lk[i][2], bb) < km;
                 }
                 const uint64_t mask = __ballot(hit);
                 uint32_t basep = 0;
@@ -533,7 +600,7 @@ __global__ __launch_bounds__(256) void k_fps_coop(
             __syncthreads();
             naff = (int)s_n;
         }
-        // update the chunks, U per wave step with 8 loads in flight per lane
+        // 2. update them: running minima, best key and point, second minimum
         for (int e0 = wid * U; e0 < naff; e0 += NW * U) {
             float4 q[8];
             float mm[8];
@@ -541,8 +608,8 @@ __global__ __launch_bounds__(256) void k_fps_coop(
             int sl[U];
 #pragma unroll
             for (int c = 0; c < U; ++c) {
-                const int e = e0 + c;
-                sl[c] = e < naff ? (init ? e : (int)s_list[e]) : -1;
+                const int ee = e0 + c;
+                sl[c] = ee < naff ? (init ? ee : (int)s_list[ee]) : -1;
             }
 #pragma unroll
             for (int i = 0; i < 8; ++i) {
@@ -562,18 +629,32 @@ __global__ __launch_bounds__(256) void k_fps_coop(
             for (int c = 0; c < U; ++c) {
                 if (sl[c] < 0) continue;
                 uint64_t kb = 0;
+                float mb = 0.f, m2 = 0.f;  // this lane's best minimum and its second
+                float bx = 0.f, by = 0.f, bz = 0.f;
                 float mn0 = INFINITY, mn1 = INFINITY, mn2 = INFINITY, mx0 = -INFINITY, mx1 = -INFINITY, mx2 = -INFINITY;
 #pragma unroll
                 for (int u = 0; u < M; ++u) {
                     const int i = c * M + u;
                     if (pp[i] < 0) continue;
-                    const float d2 = fps_d2(q[i].x, q[i].y, q[i].z, lx, ly, lz);
+                    float d2 = mm[i];
+#pragma unroll
+                    for (int t = 0; t < kJ; ++t)
+                        if (t < np) d2 = fminf(d2, fps_d2(q[i].x, q[i].y, q[i].z, lk[t][0], lk[t][1], lk[t][2]));
                     if (d2 < mm[i]) {
                         mm[i] = d2;
                         mind[pp[i]] = d2;
                     }
                     const uint64_t k = fps_key(mm[i], (uint32_t)__float_as_int(q[i].w) - base_idx);
-                    kb = k > kb ? k : kb;
+                    if (k > kb) {
+                        m2 = kb ? mb : m2;
+                        kb = k;
+                        mb = mm[i];
+                        bx = q[i].x;
+                        by = q[i].y;
+                        bz = q[i].z;
+                    } else {
+                        m2 = fmaxf(m2, mm[i]);
+                    }
                     if (init) {
                         mn0 = fminf(mn0, q[i].x); mx0 = fmaxf(mx0, q[i].x);
                         mn1 = fminf(mn1, q[i].y); mx1 = fmaxf(mx1, q[i].y);
@@ -581,6 +662,16 @@ __global__ __launch_bounds__(256) void k_fps_coop(
                     }
                 }
                 const uint64_t km = wave_max_u64(kb);
+                const uint64_t own = __ballot(kb == km && kb != 0);
+                const int src = own ? __ffsll((unsigned long long)own) - 1 : 0;
+                bx = __shfl(bx, src, 64);
+                by = __shfl(by, src, 64);
+                bz = __shfl(bz, src, 64);
+                // second minimum of the chunk: every lane's best except the
+                // chunk's best point, and every lane's second
+                float sec = lane == src ? m2 : fmaxf(mb, m2);
+#pragma unroll
+                for (int o = 32; o > 0; o >>= 1) sec = fmaxf(sec, __shfl_xor(sec, o, 64));
                 if (init) {
 #pragma unroll
                     for (int o = 32; o > 0; o >>= 1) {
@@ -592,6 +683,10 @@ __global__ __launch_bounds__(256) void k_fps_coop(
                 if (lane == 0) {
                     const int s_ = sl[c];
                     s_key[s_] = km;
+                    s_px[s_] = bx;
+                    s_px[nmine + s_] = by;
+                    s_px[2 * nmine + s_] = bz;
+                    s_sec[s_] = sec;
                     if (init) {
                         s_bb[s_] = mn0; s_bb[nmine + s_] = mn1; s_bb[2 * nmine + s_] = mn2;
                         s_bb[3 * nmine + s_] = mx0; s_bb[4 * nmine + s_] = mx1; s_bb[5 * nmine + s_] = mx2;
@@ -600,104 +695,235 @@ __global__ __launch_bounds__(256) void k_fps_coop(
             }
         }
         __syncthreads();
-        // the workgroup's max key
-        uint64_t kb = 0;
-        for (int sl = tid; sl < nmine; sl += NT) kb = s_key[sl] > kb ? s_key[sl] : kb;
-        const uint64_t km = wave_max_u64(kb);
-        if (lane == 0) s_wk[wid] = km;
-        __syncthreads();
-        if (wid == 0) {
-            const uint32_t tag = (uint32_t)(t + 1) & 3u;
-            uint64_t *ring = rk + (t & 1) * kMaxWG;
-            if (lane == 0) {
-                uint64_t k = s_wk[0];
-                for (int w = 1; w < NW; ++w) k = s_wk[w] > k ? s_wk[w] : k;
-                __hip_atomic_store(&ring[wg], ring_key(k, tag), __ATOMIC_RELAXED, SCOPE);
-            }
-            // poll the round's W slots; each slot's point is fetched from X as
-            // soon as its key shows up, so the winner's is usually on hand
-            uint64_t v[PER];
-            float cx[PER], cy[PER], cz[PER];
-            bool have[PER];
+        // 3. this workgroup's three best chunks
+        {
+            uint64_t tk[3] = {0, 0, 0};
+            int ts[3] = {-1, -1, -1};
+            for (int sl = tid; sl < nmine; sl += NT) top3_insert(tk, ts, s_key[sl], sl);
 #pragma unroll
-            for (int i = 0; i < PER; ++i) {
-                v[i] = 0;
-                cx[i] = cy[i] = cz[i] = 0.f;
-                have[i] = lane + 64 * i >= W;
+            for (int o = 32; o > 0; o >>= 1) {
+                uint64_t ok[3];
+                int os[3];
+#pragma unroll
+                for (int r = 0; r < 3; ++r) {
+                    ok[r] = __shfl_xor(tk[r], o, 64);
+                    os[r] = __shfl_xor(ts[r], o, 64);
+                }
+#pragma unroll
+                for (int r = 0; r < 3; ++r) top3_insert(tk, ts, ok[r], os[r]);
             }
+            if (lane == 0)
+#pragma unroll
+                for (int r = 0; r < 3; ++r) {
+                    s_tk[wid][r] = tk[r];
+                    s_ts[wid][r] = ts[r];
+                }
+        }
+        __syncthreads();
+        const uint32_t id = e + 1;
+        uint64_t *my_rec = rec + ((size_t)(e & 1) * kMaxWG + wg) * kRec;
+        if (tid == 0) {
+            uint64_t tk[3] = {s_tk[0][0], s_tk[0][1], s_tk[0][2]};
+            int ts[3] = {s_ts[0][0], s_ts[0][1], s_ts[0][2]};
+            for (int w = 1; w < NW; ++w)
+                for (int r = 0; r < 3; ++r) top3_insert(tk, ts, s_tk[w][r], s_ts[w][r]);
+            // 4. the record: bound of the other chunks, then kK candidates
+            __hip_atomic_store(&my_rec[0], xw(ts[kK] >= 0 ? (uint32_t)(tk[kK] >> 32) : 0u, id), __ATOMIC_RELAXED, SCOPE);
+            for (int c = 0; c < kK; ++c) {
+                uint32_t v[12];
+                const int s_ = ts[c];
+                if (s_ >= 0) {
+                    v[0] = (uint32_t)(tk[c] >> 32);
+                    v[1] = 0xffffffffu - (uint32_t)tk[c];
+                    v[2] = __float_as_uint(s_px[s_]);
+                    v[3] = __float_as_uint(s_px[nmine + s_]);
+                    v[4] = __float_as_uint(s_px[2 * nmine + s_]);
+                    v[5] = __float_as_uint(s_sec[s_]);
+                    for (int b = 0; b < 6; ++b) v[6 + b] = __float_as_uint(s_bb[b * nmine + s_]);
+                } else {
+                    for (int b = 0; b < 12; ++b) v[b] = 0u;
+                    v[1] = 0xffffffffu;  // no candidate
+                }
+                for (int b = 0; b < 12; ++b)
+                    __hip_atomic_store(&my_rec[1 + 12 * c + b], xw(v[b], id), __ATOMIC_RELAXED, SCOPE);
+            }
+        }
+        uint64_t *my_dec = dec + (size_t)(e & 1) * kDec;
+        const int jcap = min(kJ, a.nl + 1 - t_done);
+        if (wg == 0 && wid == 0) {
+            // 5. the leader: collect the records, replay the greedy rule
+            float cm[PER][kK], cxp[PER][kK], cyp[PER][kK], czp[PER][kK], cb[PER][kK], cbb[PER][kK][6];
+            uint32_t cid[PER][kK];
+            float bw[PER];
+            bool valid[PER][kK];
             bool done = false;
-            for (int spin = 0; spin < kSpinLimit; ++spin) {
+            for (int spin = 0; spin < kSpinLimit && !done; ++spin) {
                 bool ok = true;
 #pragma unroll
-                for (int i = 0; i < PER; ++i) {
-                    if (have[i]) continue;
-                    const uint64_t x = __hip_atomic_load(&ring[lane + 64 * i], __ATOMIC_RELAXED, SCOPE);
-                    if ((((uint32_t)x >> 30) & 3u) == tag) {
-                        have[i] = true;
-                        v[i] = x;
-                        const int64_t row = pb + (int64_t)(0x3fffffffu - ((uint32_t)x & 0x3fffffffu));
-                        cx[i] = X[3 * row];
-                        cy[i] = X[3 * row + 1];
-                        cz[i] = X[3 * row + 2];
-                    } else {
-                        ok = false;
+                for (int r = 0; r < PER; ++r) {
+                    const int w = lane + 64 * r;
+                    bw[r] = 0.f;
+#pragma unroll
+                    for (int c = 0; c < kK; ++c) valid[r][c] = false;
+                    if (w >= W) continue;
+                    const uint64_t *rw = rec + ((size_t)(e & 1) * kMaxWG + w) * kRec;
+                    const uint64_t w0 = __hip_atomic_load(&rw[0], __ATOMIC_RELAXED, SCOPE);
+                    ok &= xw_ok(w0, id);
+                    bw[r] = __uint_as_float(xw_val(w0));
+#pragma unroll
+                    for (int c = 0; c < kK; ++c) {
+                        uint32_t v[12];
+#pragma unroll
+                        for (int b = 0; b < 12; ++b) {
+                            const uint64_t x = __hip_atomic_load(&rw[1 + 12 * c + b], __ATOMIC_RELAXED, SCOPE);
+                            ok &= xw_ok(x, id);
+                            v[b] = xw_val(x);
+                        }
+                        valid[r][c] = v[1] != 0xffffffffu;
+                        cm[r][c] = __uint_as_float(v[0]);
+                        cid[r][c] = v[1];
+                        cxp[r][c] = __uint_as_float(v[2]);
+                        cyp[r][c] = __uint_as_float(v[3]);
+                        czp[r][c] = __uint_as_float(v[4]);
+                        cb[r][c] = __uint_as_float(v[5]);
+#pragma unroll
+                        for (int b = 0; b < 6; ++b) cbb[r][c][b] = __uint_as_float(v[6 + b]);
                     }
                 }
-                if (__all(ok)) {
-                    done = true;
-                    break;
+                done = __all(ok);
+                if (!done) __builtin_amdgcn_s_sleep(1);
+            }
+            if (!done) {
+                if (lane == 0) {
+                    __hip_atomic_store(err, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    __hip_atomic_store(&my_dec[0], xw(0u, id), __ATOMIC_RELAXED, SCOPE);  // j = 0: abort
+                }
+            } else {
+                int j = 0;
+                for (int p = 0; p < jcap; ++p) {
+                    uint64_t lo = 0, hi = 0;
+                    int lr = 0, lc = 0;
+#pragma unroll
+                    for (int r = 0; r < PER; ++r) {
+                        if (lane + 64 * r >= W) continue;
+                        hi = max(hi, key_bound(bw[r]));
+#pragma unroll
+                        for (int c = 0; c < kK; ++c) {
+                            if (!valid[r][c]) continue;
+                            hi = max(hi, key_bound(cb[r][c]));
+                            const uint64_t k = ((uint64_t)__float_as_uint(cm[r][c]) << 32) | (uint64_t)(0xffffffffu - cid[r][c]);
+                            if (k > lo) {
+                                lo = k;
+                                lr = r;
+                                lc = c;
+                            }
+                        }
+                    }
+                    const uint64_t best = wave_max_u64(lo);
+                    const uint64_t bound = wave_max_u64(hi);
+                    if (p > 0 && !(best > bound)) break;
+                    const uint64_t own = __ballot(lo == best && lo != 0);
+                    const int src = own ? __ffsll((unsigned long long)own) - 1 : 0;
+                    float px = 0.f, py = 0.f, pz = 0.f;
+#pragma unroll
+                    for (int r = 0; r < PER; ++r)
+#pragma unroll
+                        for (int c = 0; c < kK; ++c)
+                            if (r == lr && c == lc) {
+                                px = cxp[r][c];
+                                py = cyp[r][c];
+                                pz = czp[r][c];
+                            }
+                    px = __shfl(px, src, 64);
+                    py = __shfl(py, src, 64);
+                    pz = __shfl(pz, src, 64);
+                    if (lane == 0) {
+                        const uint32_t w5[5] = {0xffffffffu - (uint32_t)best, (uint32_t)(best >> 32), __float_as_uint(px),
+                                                __float_as_uint(py), __float_as_uint(pz)};
+                        for (int b = 0; b < 5; ++b)
+                            __hip_atomic_store(&my_dec[1 + 5 * p + b], xw(w5[b], id), __ATOMIC_RELAXED, SCOPE);
+                    }
+                    ++j;
+                    // the candidates and the chunk bounds after this pick
+#pragma unroll
+                    for (int r = 0; r < PER; ++r)
+#pragma unroll
+                        for (int c = 0; c < kK; ++c) {
+                            if (!valid[r][c]) continue;
+                            cm[r][c] = fminf(cm[r][c], fps_d2(cxp[r][c], cyp[r][c], czp[r][c], px, py, pz));
+                            cb[r][c] = fminf(cb[r][c], fps_box_far_d2(px, py, pz, cbb[r][c]));
+                        }
+                }
+                if (lane == 0) __hip_atomic_store(&my_dec[0], xw((uint32_t)j, id), __ATOMIC_RELAXED, SCOPE);
+            }
+        }
+        // 6. every workgroup reads the decision
+        if (wid == 0) {
+            uint64_t x = 0;
+            bool done = false;
+            int j = 0;
+            for (int spin = 0; spin < kSpinLimit; ++spin) {
+                x = lane <= 5 * kJ ? __hip_atomic_load(&my_dec[lane], __ATOMIC_RELAXED, SCOPE) : 0;
+                const uint64_t w0 = __shfl(x, 0, 64);
+                if (xw_ok(w0, id)) {
+                    j = (int)xw_val(w0);
+                    const bool need = lane >= 1 && lane <= 5 * j;
+                    if (__all(!need || xw_ok(x, id))) {
+                        done = true;
+                        break;
+                    }
                 }
                 __builtin_amdgcn_s_sleep(1);
             }
-            uint64_t mk = 0;
-            float bx = 0.f, by = 0.f, bz = 0.f;
-#pragma unroll
-            for (int i = 0; i < PER; ++i)
-                if (v[i] > mk) {
-                    mk = v[i];
-                    bx = cx[i];
-                    by = cy[i];
-                    bz = cz[i];
-                }
-            const uint64_t best = wave_max_u64(mk);
-            const uint64_t own = __ballot(mk == best);
-            const int src = __ffsll((unsigned long long)own) - 1;
-            bx = __shfl(bx, src, 64);
-            by = __shfl(by, src, 64);
-            bz = __shfl(bz, src, 64);
             if (lane == 0) {
-                if (!done) {
+                if (!done || j == 0) {
                     __hip_atomic_store(err, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                     s_abort = 1;
                     if (wg == 0)
-                        for (int tt = t + 1; tt < a.nl; ++tt) idx_out[a.lo + tt] = -1;
-                } else {
-                    s_l[0] = bx;
-                    s_l[1] = by;
-                    s_l[2] = bz;
-                    if (wg == 0) {
-                        if (radius) radius[a.lo + t] = sqrt_rn(__uint_as_float((uint32_t)(best >> 32)));
-                        if (t + 1 < a.nl) idx_out[a.lo + t + 1] = (int32_t)(0x3fffffffu - ((uint32_t)best & 0x3fffffffu));
+                        for (int tt = t_done; tt < a.nl; ++tt) idx_out[a.lo + tt] = -1;
+                }
+                s_j = j;
+            }
+            if (done && j > 0) {
+                // pick p's words sit in lanes 1 + 5p .. 5 + 5p
+                for (int p = 0; p < j; ++p) {
+                    const uint32_t pidx = xw_val(__shfl(x, 1 + 5 * p, 64));
+                    const float pm = __uint_as_float(xw_val(__shfl(x, 2 + 5 * p, 64)));
+                    const float px = __uint_as_float(xw_val(__shfl(x, 3 + 5 * p, 64)));
+                    const float py = __uint_as_float(xw_val(__shfl(x, 4 + 5 * p, 64)));
+                    const float pz = __uint_as_float(xw_val(__shfl(x, 5 + 5 * p, 64)));
+                    const int slot = t_done + p;  // landmark slot this pick decides
+                    if (lane == 0) {
+                        if (slot < a.nl) {
+                            s_pk[p][0] = px;
+                            s_pk[p][1] = py;
+                            s_pk[p][2] = pz;
+                        }
+                        if (wg == 0) {
+                            if (radius) radius[a.lo + slot - 1] = sqrt_rn(pm);
+                            if (slot < a.nl) idx_out[a.lo + slot] = (int32_t)pidx;
+                        }
                     }
                 }
+                if (lane == 0) s_np = min(j, a.nl - t_done);
             }
         }
         __syncthreads();
         if (s_abort) return;
+        t_done += s_j;
+        if (t_done > a.nl) return;  // the last pick only gave the final covering radius
     }
 }
 
 template <int LM>
 static hipError_t launch_coop(const CoopArgs &a, int grid, int shmem, const float *X, const GridParam *gp,
-                              const float4 *xs, float *mind, uint64_t *rk, uint32_t *ctl, const int64_t *start,
-                              int32_t *idx, float *radius, hipStream_t s) {
-    hipError_t e = hipFuncSetAttribute((const void *)k_fps_coop<LM>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, shmem);
+                              const float4 *xs, float *mind, uint64_t *rec, uint64_t *dec, uint32_t *ctl,
+                              const int64_t *start, int32_t *idx, float *radius, hipStream_t s) {
+    hipError_t e = hipFuncSetAttribute((const void *)k_fps_coop<LM>, hipFuncAttributeMaxDynamicSharedMemorySize, shmem);
     if (e != hipSuccess) return e;
     CoopArgs aa = a;
-    void *args[] = {&aa, (void *)&X, (void *)&gp, (void *)&xs, &mind, &rk, &ctl, (void *)&start, &idx, &radius};
-    return hipLaunchCooperativeKernel((const void *)k_fps_coop<LM>, dim3(grid), dim3(256),
-                                      args, (unsigned)shmem, s);
+    void *args[] = {&aa, (void *)&X, (void *)&gp, (void *)&xs, &mind, &rec, &dec, &ctl, (void *)&start, &idx, &radius};
+    return hipLaunchCooperativeKernel((const void *)k_fps_coop<LM>, dim3(grid), dim3(256), args, (unsigned)shmem, s);
 }
 
 static int device_cus() {
@@ -717,7 +943,7 @@ struct CoopShape {
 // the cooperative launch of a cloud of n points (one workgroup per CU, at
 // least 16 chunks each); false: the persistent path
 static bool coop_shape(int64_t n, int cus, CoopShape *cs) {
-    if (n < kCoopMin || n >= kCoopMaxPts || cus < 1) return false;
+    if (n < kCoopMin || cus < 1) return false;
     const int64_t wmax = std::min<int64_t>(cus, kMaxWG);
     for (int l = 0; l <= 3; ++l) {
         const int64_t nc = (n + (64 << l) - 1) / (64 << l);
@@ -727,17 +953,18 @@ static bool coop_shape(int64_t n, int cus, CoopShape *cs) {
             cs->nwg = (int32_t)w;
             cs->lm = l;
             cs->nchunk = nc;
-            cs->shmem = (int)(cpw * 36);
+            cs->shmem = (int)(cpw * 52);
             return true;
         }
     }
     return false;
 }
 
-// clouds below this size (and at least kCoopMin) take a cooperative path
+// clouds below this size (and at least kCoopMin) take the cooperative path:
+// their chunk slots fit in LDS with m <= 8 on every workgroup
 static int64_t coop_limit(int cus) {
     const int64_t wmax = std::min<int64_t>(cus, kMaxWG);
-    return std::min<int64_t>(kCoopMaxPts, wmax * kMaxCpw * 512);
+    return std::min<int64_t>((int64_t)1 << 31, wmax * kMaxCpw * 512);
 }
 
 hipError_t fps_run(const float *X, int32_t B, const int64_t *x_off, const int64_t *x_off_d,
@@ -753,7 +980,8 @@ hipError_t fps_run(const float *X, int32_t B, const int64_t *x_off, const int64_
     w.rkey = c.take<uint64_t>(tc + 1);
     w.state = c.take<FpsState>(B);
     w.l_off = c.take<int64_t>(B + 1);
-    uint64_t *ring_k = c.take<uint64_t>(2 * kMaxWG);
+    uint64_t *rec = c.take<uint64_t>((size_t)2 * kMaxWG * kRec);
+    uint64_t *dec = c.take<uint64_t>((size_t)2 * kDec);
     uint32_t *ctl = c.take<uint32_t>(1);  // error flag of the cooperative launches
     if (!c.ok()) return hipErrorOutOfMemory;
     const int cus = device_cus();
@@ -772,7 +1000,9 @@ hipError_t fps_run(const float *X, int32_t B, const int64_t *x_off, const int64_
         const int64_t n = x_off[b + 1] - x_off[b];
         CoopShape cs;
         if (n >= kCoopMin && n < coop_hi && coop_shape(n, cus, &cs)) {
-            e = fill_u64(ring_k, 0ull, 2 * kMaxWG, s);
+            e = fill_u64(rec, 0ull, (int64_t)2 * kMaxWG * kRec, s);
+            if (e != hipSuccess) return e;
+            e = fill_u64(dec, 0ull, 2 * kDec, s);
             if (e != hipSuccess) return e;
             CoopArgs a;
             a.b = b;
@@ -781,7 +1011,7 @@ hipError_t fps_run(const float *X, int32_t B, const int64_t *x_off, const int64_
             a.pad = 0;
             a.nchunk = cs.nchunk;
             a.lo = lo;
-#define FLOOD_COOP(LM_) launch_coop<LM_>(a, cs.nwg, cs.shmem, X, w.grid.gp, w.grid.xs, w.mind, ring_k, ctl, start_d, idx, radius, s)
+#define FLOOD_COOP(LM_) launch_coop<LM_>(a, cs.nwg, cs.shmem, X, w.grid.gp, w.grid.xs, w.mind, rec, dec, ctl, start_d, idx, radius, s)
             switch (cs.lm) {
                 case 0: e = FLOOD_COOP(0); break;
                 case 1: e = FLOOD_COOP(1); break;
