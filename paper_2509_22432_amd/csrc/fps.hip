@@ -33,7 +33,7 @@ static constexpr int kU = 8;           // points per thread per step
 static constexpr int kMaxDim = 1024;   // cells per axis of a row grid (slab keys fit in LDS)
 static constexpr int kMaxWG = 256;     // workgroups of one cooperative launch
 static constexpr int kRec = 32;        // 64-bit words of a workgroup's record in an exchange
-static constexpr int kDec = 48;        // 64-bit words of an exchange's decision
+static constexpr int kDec = 96;        // 64-bit words of an exchange's decision
 
 struct FpsState {
     int32_t cur;  // local index of the newest landmark
@@ -461,7 +461,7 @@ static constexpr int kMaxCpw = 2816;              // chunk slots per workgroup (
 static constexpr int64_t kCoopMin = 1 << 19;      // clouds of at least this many points
 static constexpr int kSpinLimit = 1 << 22;        // polls of one exchange before the launch gives up
 static constexpr int kK = 2;                      // candidates a workgroup publishes
-static constexpr int kJ = 8;                      // landmarks decided per exchange, at most
+static constexpr int kJ = 16;                     // landmarks decided per exchange, at most
 
 struct CoopArgs {
     int32_t b;       // cloud
@@ -529,15 +529,22 @@ __global__ __launch_bounds__(256) void k_fps_coop(
     constexpr int NW = NT / 64;
     constexpr int M = 1 << LM;          // points per lane per chunk
     constexpr int U = 8 >> LM;          // chunks per wave step
-    constexpr int PER = kMaxWG / 64;    // workgroup records a lane of the leader reads
     constexpr int SCOPE = __HIP_MEMORY_SCOPE_AGENT;
-    static_assert(1 + 12 * kK <= kRec && 1 + 5 * kJ <= kDec && 1 + 5 * kJ <= 64, "exchange layout");
+    static_assert(1 + 12 * kK <= kRec && 1 + 12 * kK <= 64 && 1 + 5 * kJ <= kDec && 1 + 5 * kJ <= 128 && kK <= 2,
+                  "exchange layout");
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ float s_pk[kJ][3];       // landmarks to apply
     __shared__ int s_np, s_j, s_abort;
     __shared__ uint32_t s_n;
     __shared__ uint64_t s_tk[NW][3];
     __shared__ int s_ts[NW][3];
+    struct Red {
+        uint64_t key, bound;
+        float x, y, z;
+    };
+    __shared__ Red s_red[2][NW];         // the leader's per-wave reductions (double-buffered)
+    __shared__ uint32_t s_pick[kJ][5];   // the leader's picks
+    __shared__ int s_wok[NW];
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     const int W = a.nwg;
     const int wg = blockIdx.x;
@@ -722,153 +729,181 @@ __global__ __launch_bounds__(256) void k_fps_coop(
         __syncthreads();
         const uint32_t id = e + 1;
         uint64_t *my_rec = rec + ((size_t)(e & 1) * kMaxWG + wg) * kRec;
-        if (tid == 0) {
+        if (wid == 0) {
+            // 4. the record, one word per lane: bound of the other chunks,
+            //    then kK candidates of 12 words
             uint64_t tk[3] = {s_tk[0][0], s_tk[0][1], s_tk[0][2]};
             int ts[3] = {s_ts[0][0], s_ts[0][1], s_ts[0][2]};
             for (int w = 1; w < NW; ++w)
+#pragma unroll
                 for (int r = 0; r < 3; ++r) top3_insert(tk, ts, s_tk[w][r], s_ts[w][r]);
-            // 4. the record: bound of the other chunks, then kK candidates
-            __hip_atomic_store(&my_rec[0], xw(ts[kK] >= 0 ? (uint32_t)(tk[kK] >> 32) : 0u, id), __ATOMIC_RELAXED, SCOPE);
-            for (int c = 0; c < kK; ++c) {
-                uint32_t v[12];
-                const int s_ = ts[c];
-                if (s_ >= 0) {
-                    v[0] = (uint32_t)(tk[c] >> 32);
-                    v[1] = 0xffffffffu - (uint32_t)tk[c];
-                    v[2] = __float_as_uint(s_px[s_]);
-                    v[3] = __float_as_uint(s_px[nmine + s_]);
-                    v[4] = __float_as_uint(s_px[2 * nmine + s_]);
-                    v[5] = __float_as_uint(s_sec[s_]);
-                    for (int b = 0; b < 6; ++b) v[6 + b] = __float_as_uint(s_bb[b * nmine + s_]);
-                } else {
-                    for (int b = 0; b < 12; ++b) v[b] = 0u;
-                    v[1] = 0xffffffffu;  // no candidate
-                }
-                for (int b = 0; b < 12; ++b)
-                    __hip_atomic_store(&my_rec[1 + 12 * c + b], xw(v[b], id), __ATOMIC_RELAXED, SCOPE);
+            uint32_t v = 0;
+            if (lane == 0) {
+                v = ts[kK] >= 0 ? (uint32_t)(tk[kK] >> 32) : 0u;
+            } else if (lane <= 12 * kK) {
+                const int c = (lane - 1) / 12, f = (lane - 1) % 12;
+                const int s_ = c == 0 ? ts[0] : (c == 1 ? ts[1] : ts[2]);
+                const uint64_t kc = c == 0 ? tk[0] : (c == 1 ? tk[1] : tk[2]);
+                if (s_ < 0) v = f == 1 ? 0xffffffffu : 0u;  // no candidate
+                else if (f == 0) v = (uint32_t)(kc >> 32);
+                else if (f == 1) v = 0xffffffffu - (uint32_t)kc;
+                else if (f <= 4) v = __float_as_uint(s_px[(f - 2) * nmine + s_]);
+                else if (f == 5) v = __float_as_uint(s_sec[s_]);
+                else v = __float_as_uint(s_bb[(f - 6) * nmine + s_]);
             }
+            if (lane <= 12 * kK) __hip_atomic_store(&my_rec[lane], xw(v, id), __ATOMIC_RELAXED, SCOPE);
         }
         uint64_t *my_dec = dec + (size_t)(e & 1) * kDec;
         const int jcap = min(kJ, a.nl + 1 - t_done);
-        if (wg == 0 && wid == 0) {
-            // 5. the leader: collect the records, replay the greedy rule
-            float cm[PER][kK], cxp[PER][kK], cyp[PER][kK], czp[PER][kK], cb[PER][kK], cbb[PER][kK][6];
-            uint32_t cid[PER][kK];
-            float bw[PER];
-            bool valid[PER][kK];
+        if (wg == 0) {
+            // 5. the leader: every lane collects one workgroup's record, then
+            //    the four waves replay the greedy rule together
+            const int w = wid * 64 + lane;
+            float cm[kK], cxp[kK], cyp[kK], czp[kK], cb[kK], cbb[kK][6], bw = 0.f;
+            uint32_t cid[kK];
+            bool valid[kK];
             bool done = false;
             for (int spin = 0; spin < kSpinLimit && !done; ++spin) {
                 bool ok = true;
 #pragma unroll
-                for (int r = 0; r < PER; ++r) {
-                    const int w = lane + 64 * r;
-                    bw[r] = 0.f;
-#pragma unroll
-                    for (int c = 0; c < kK; ++c) valid[r][c] = false;
-                    if (w >= W) continue;
+                for (int c = 0; c < kK; ++c) valid[c] = false;
+                if (w < W) {
                     const uint64_t *rw = rec + ((size_t)(e & 1) * kMaxWG + w) * kRec;
                     const uint64_t w0 = __hip_atomic_load(&rw[0], __ATOMIC_RELAXED, SCOPE);
                     ok &= xw_ok(w0, id);
-                    bw[r] = __uint_as_float(xw_val(w0));
+                    bw = __uint_as_float(xw_val(w0));
 #pragma unroll
                     for (int c = 0; c < kK; ++c) {
                         uint32_t v[12];
 #pragma unroll
-                        for (int b = 0; b < 12; ++b) {
-                            const uint64_t x = __hip_atomic_load(&rw[1 + 12 * c + b], __ATOMIC_RELAXED, SCOPE);
+                        for (int f = 0; f < 12; ++f) {
+                            const uint64_t x = __hip_atomic_load(&rw[1 + 12 * c + f], __ATOMIC_RELAXED, SCOPE);
                             ok &= xw_ok(x, id);
-                            v[b] = xw_val(x);
+                            v[f] = xw_val(x);
                         }
-                        valid[r][c] = v[1] != 0xffffffffu;
-                        cm[r][c] = __uint_as_float(v[0]);
-                        cid[r][c] = v[1];
-                        cxp[r][c] = __uint_as_float(v[2]);
-                        cyp[r][c] = __uint_as_float(v[3]);
-                        czp[r][c] = __uint_as_float(v[4]);
-                        cb[r][c] = __uint_as_float(v[5]);
+                        valid[c] = v[1] != 0xffffffffu;
+                        cm[c] = __uint_as_float(v[0]);
+                        cid[c] = v[1];
+                        cxp[c] = __uint_as_float(v[2]);
+                        cyp[c] = __uint_as_float(v[3]);
+                        czp[c] = __uint_as_float(v[4]);
+                        cb[c] = __uint_as_float(v[5]);
 #pragma unroll
-                        for (int b = 0; b < 6; ++b) cbb[r][c][b] = __uint_as_float(v[6 + b]);
+                        for (int f = 0; f < 6; ++f) cbb[c][f] = __uint_as_float(v[6 + f]);
                     }
                 }
                 done = __all(ok);
                 if (!done) __builtin_amdgcn_s_sleep(1);
             }
-            if (!done) {
-                if (lane == 0) {
-                    __hip_atomic_store(err, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    __hip_atomic_store(&my_dec[0], xw(0u, id), __ATOMIC_RELAXED, SCOPE);  // j = 0: abort
-                }
-            } else {
-                int j = 0;
+            if (lane == 0) s_wok[wid] = done ? 1 : 0;
+            __syncthreads();
+            const bool all_in = s_wok[0] && s_wok[1] && s_wok[2] && s_wok[3];
+            int j = 0;
+            if (all_in) {
                 for (int p = 0; p < jcap; ++p) {
                     uint64_t lo = 0, hi = 0;
-                    int lr = 0, lc = 0;
-#pragma unroll
-                    for (int r = 0; r < PER; ++r) {
-                        if (lane + 64 * r >= W) continue;
-                        hi = max(hi, key_bound(bw[r]));
+                    int lc = 0;
+                    if (w < W) {
+                        hi = key_bound(bw);
 #pragma unroll
                         for (int c = 0; c < kK; ++c) {
-                            if (!valid[r][c]) continue;
-                            hi = max(hi, key_bound(cb[r][c]));
-                            const uint64_t k = ((uint64_t)__float_as_uint(cm[r][c]) << 32) | (uint64_t)(0xffffffffu - cid[r][c]);
+                            if (!valid[c]) continue;
+                            hi = max(hi, key_bound(cb[c]));
+                            const uint64_t k = ((uint64_t)__float_as_uint(cm[c]) << 32) | (uint64_t)(0xffffffffu - cid[c]);
                             if (k > lo) {
                                 lo = k;
-                                lr = r;
                                 lc = c;
                             }
                         }
                     }
                     const uint64_t best = wave_max_u64(lo);
                     const uint64_t bound = wave_max_u64(hi);
-                    if (p > 0 && !(best > bound)) break;
                     const uint64_t own = __ballot(lo == best && lo != 0);
                     const int src = own ? __ffsll((unsigned long long)own) - 1 : 0;
                     float px = 0.f, py = 0.f, pz = 0.f;
 #pragma unroll
-                    for (int r = 0; r < PER; ++r)
-#pragma unroll
-                        for (int c = 0; c < kK; ++c)
-                            if (r == lr && c == lc) {
-                                px = cxp[r][c];
-                                py = cyp[r][c];
-                                pz = czp[r][c];
-                            }
+                    for (int c = 0; c < kK; ++c)
+                        if (c == lc) {
+                            px = cxp[c];
+                            py = cyp[c];
+                            pz = czp[c];
+                        }
                     px = __shfl(px, src, 64);
                     py = __shfl(py, src, 64);
                     pz = __shfl(pz, src, 64);
                     if (lane == 0) {
-                        const uint32_t w5[5] = {0xffffffffu - (uint32_t)best, (uint32_t)(best >> 32), __float_as_uint(px),
-                                                __float_as_uint(py), __float_as_uint(pz)};
-                        for (int b = 0; b < 5; ++b)
-                            __hip_atomic_store(&my_dec[1 + 5 * p + b], xw(w5[b], id), __ATOMIC_RELAXED, SCOPE);
+                        s_red[p & 1][wid].key = best;
+                        s_red[p & 1][wid].bound = bound;
+                        s_red[p & 1][wid].x = px;
+                        s_red[p & 1][wid].y = py;
+                        s_red[p & 1][wid].z = pz;
+                    }
+                    __syncthreads();
+                    int bwv = 0;
+                    uint64_t gb = s_red[p & 1][0].key, gh = s_red[p & 1][0].bound;
+#pragma unroll
+                    for (int v = 1; v < NW; ++v) {
+                        const uint64_t kv = s_red[p & 1][v].key;
+                        if (kv > gb) {
+                            gb = kv;
+                            bwv = v;
+                        }
+                        gh = max(gh, s_red[p & 1][v].bound);
+                    }
+                    if (p > 0 && !(gb > gh)) break;  // the same decision in every wave
+                    px = s_red[p & 1][bwv].x;
+                    py = s_red[p & 1][bwv].y;
+                    pz = s_red[p & 1][bwv].z;
+                    if (tid == 0) {
+                        s_pick[p][0] = 0xffffffffu - (uint32_t)gb;
+                        s_pick[p][1] = (uint32_t)(gb >> 32);
+                        s_pick[p][2] = __float_as_uint(px);
+                        s_pick[p][3] = __float_as_uint(py);
+                        s_pick[p][4] = __float_as_uint(pz);
                     }
                     ++j;
                     // the candidates and the chunk bounds after this pick
 #pragma unroll
-                    for (int r = 0; r < PER; ++r)
-#pragma unroll
-                        for (int c = 0; c < kK; ++c) {
-                            if (!valid[r][c]) continue;
-                            cm[r][c] = fminf(cm[r][c], fps_d2(cxp[r][c], cyp[r][c], czp[r][c], px, py, pz));
-                            cb[r][c] = fminf(cb[r][c], fps_box_far_d2(px, py, pz, cbb[r][c]));
-                        }
+                    for (int c = 0; c < kK; ++c) {
+                        if (!valid[c]) continue;
+                        cm[c] = fminf(cm[c], fps_d2(cxp[c], cyp[c], czp[c], px, py, pz));
+                        cb[c] = fminf(cb[c], fps_box_far_d2(px, py, pz, cbb[c]));
+                    }
                 }
-                if (lane == 0) __hip_atomic_store(&my_dec[0], xw((uint32_t)j, id), __ATOMIC_RELAXED, SCOPE);
+            }
+            __syncthreads();
+            if (wid == 0) {
+                // the decision, one word per lane: j, then 5 words per pick
+                if (!all_in) {
+                    if (lane == 0) {
+                        __hip_atomic_store(err, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        __hip_atomic_store(&my_dec[0], xw(0u, id), __ATOMIC_RELAXED, SCOPE);  // j = 0: abort
+                    }
+                } else {
+#pragma unroll
+                    for (int h = 0; h < 2; ++h) {
+                        const int i = lane + 64 * h;
+                        if (i > 5 * j) continue;
+                        const uint32_t v = i == 0 ? (uint32_t)j : s_pick[(i - 1) / 5][(i - 1) % 5];
+                        __hip_atomic_store(&my_dec[i], xw(v, id), __ATOMIC_RELAXED, SCOPE);
+                    }
+                }
             }
         }
-        // 6. every workgroup reads the decision
+        // 6. every workgroup reads the decision (words lane and lane + 64)
         if (wid == 0) {
-            uint64_t x = 0;
+            uint64_t x0 = 0, x1 = 0;
             bool done = false;
             int j = 0;
             for (int spin = 0; spin < kSpinLimit; ++spin) {
-                x = lane <= 5 * kJ ? __hip_atomic_load(&my_dec[lane], __ATOMIC_RELAXED, SCOPE) : 0;
-                const uint64_t w0 = __shfl(x, 0, 64);
+                x0 = __hip_atomic_load(&my_dec[lane], __ATOMIC_RELAXED, SCOPE);
+                x1 = lane + 64 <= 5 * kJ ? __hip_atomic_load(&my_dec[lane + 64], __ATOMIC_RELAXED, SCOPE) : 0;
+                const uint64_t w0 = __shfl(x0, 0, 64);
                 if (xw_ok(w0, id)) {
                     j = (int)xw_val(w0);
-                    const bool need = lane >= 1 && lane <= 5 * j;
-                    if (__all(!need || xw_ok(x, id))) {
+                    const bool ok0 = !(lane >= 1 && lane <= 5 * j) || xw_ok(x0, id);
+                    const bool ok1 = !(lane + 64 <= 5 * j) || xw_ok(x1, id);
+                    if (__all(ok0 && ok1)) {
                         done = true;
                         break;
                     }
@@ -885,13 +920,15 @@ __global__ __launch_bounds__(256) void k_fps_coop(
                 s_j = j;
             }
             if (done && j > 0) {
-                // pick p's words sit in lanes 1 + 5p .. 5 + 5p
+                auto word = [&](int i) -> uint32_t {
+                    return xw_val(i < 64 ? __shfl(x0, i, 64) : __shfl(x1, i - 64, 64));
+                };
                 for (int p = 0; p < j; ++p) {
-                    const uint32_t pidx = xw_val(__shfl(x, 1 + 5 * p, 64));
-                    const float pm = __uint_as_float(xw_val(__shfl(x, 2 + 5 * p, 64)));
-                    const float px = __uint_as_float(xw_val(__shfl(x, 3 + 5 * p, 64)));
-                    const float py = __uint_as_float(xw_val(__shfl(x, 4 + 5 * p, 64)));
-                    const float pz = __uint_as_float(xw_val(__shfl(x, 5 + 5 * p, 64)));
+                    const uint32_t pidx = word(1 + 5 * p);
+                    const float pm = __uint_as_float(word(2 + 5 * p));
+                    const float px = __uint_as_float(word(3 + 5 * p));
+                    const float py = __uint_as_float(word(4 + 5 * p));
+                    const float pz = __uint_as_float(word(5 + 5 * p));
                     const int slot = t_done + p;  // landmark slot this pick decides
                     if (lane == 0) {
                         if (slot < a.nl) {
