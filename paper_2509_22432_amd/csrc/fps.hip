@@ -91,6 +91,49 @@ __device__ __forceinline__ uint64_t wave_max_u64(uint64_t v) {
     return v;
 }
 
+// DPP lane moves within rows of 16 lanes (quad_perm xor 1, xor 2, then the
+// half-row and row mirrors): after the four steps every lane of a row holds
+// the row's reduction; the four rows are combined through scalar reads
+template <int CTRL>
+__device__ __forceinline__ uint32_t dpp_mov(uint32_t v) {
+    return (uint32_t)__builtin_amdgcn_update_dpp((int)v, (int)v, CTRL, 0xf, 0xf, false);
+}
+__device__ __forceinline__ uint32_t rd_lane(uint32_t v, int l) { return (uint32_t)__builtin_amdgcn_readlane((int)v, l); }
+
+template <int CTRL>
+__device__ __forceinline__ void dpp_max_step(uint32_t &hi, uint32_t &lo) {
+    const uint32_t h = dpp_mov<CTRL>(hi), l = dpp_mov<CTRL>(lo);
+    const bool take = h > hi || (h == hi && l > lo);
+    hi = take ? h : hi;
+    lo = take ? l : lo;
+}
+
+// wave-wide maximum, the same in every lane (all 64 lanes active)
+__device__ __forceinline__ uint64_t wave_max_u64_dpp(uint64_t v) {
+    uint32_t hi = (uint32_t)(v >> 32), lo = (uint32_t)v;
+    dpp_max_step<0xb1>(hi, lo);
+    dpp_max_step<0x4e>(hi, lo);
+    dpp_max_step<0x141>(hi, lo);
+    dpp_max_step<0x140>(hi, lo);
+    uint64_t r = ((uint64_t)rd_lane(hi, 0) << 32) | rd_lane(lo, 0);
+#pragma unroll
+    for (int row = 16; row < 64; row += 16) {
+        const uint64_t x = ((uint64_t)rd_lane(hi, row) << 32) | rd_lane(lo, row);
+        r = x > r ? x : r;
+    }
+    return r;
+}
+
+__device__ __forceinline__ float wave_max_f32_dpp(float v) {
+    v = fmaxf(v, __uint_as_float(dpp_mov<0xb1>(__float_as_uint(v))));
+    v = fmaxf(v, __uint_as_float(dpp_mov<0x4e>(__float_as_uint(v))));
+    v = fmaxf(v, __uint_as_float(dpp_mov<0x141>(__float_as_uint(v))));
+    v = fmaxf(v, __uint_as_float(dpp_mov<0x140>(__float_as_uint(v))));
+    const float a = fmaxf(__uint_as_float(rd_lane(__float_as_uint(v), 0)), __uint_as_float(rd_lane(__float_as_uint(v), 16)));
+    const float b = fmaxf(__uint_as_float(rd_lane(__float_as_uint(v), 32)), __uint_as_float(rd_lane(__float_as_uint(v), 48)));
+    return fmaxf(a, b);
+}
+
 __device__ __forceinline__ void finish_round(int32_t t, int32_t nl, uint64_t k, int64_t o, int64_t pt_base,
                                              const float *__restrict__ X, int32_t *__restrict__ idx_out,
                                              float *__restrict__ radius, float &lx, float &ly, float &lz,
@@ -473,11 +516,16 @@ struct CoopArgs {
 };
 
 // lower bound of fps_d2 over a box, with the same operations: each rounded
-// operation is monotone, so no point of the box can score below it
+// operation is monotone, so no point of the box can score below it.  Per
+// axis the distance to the slab is max(lo - l, l - hi, 0): at most one of the
+// two rounded differences is positive (a rounded difference keeps its sign).
+__device__ __forceinline__ float slab_d(float l, float lo, float hi) {
+    return fmaxf(fmaxf(__fsub_rn(lo, l), __fsub_rn(l, hi)), 0.f);
+}
 __device__ __forceinline__ float fps_box_d2(float lx, float ly, float lz, const float *bb) {
-    const float dx = lx < bb[0] ? __fsub_rn(bb[0], lx) : (lx > bb[3] ? __fsub_rn(lx, bb[3]) : 0.f);
-    const float dy = ly < bb[1] ? __fsub_rn(bb[1], ly) : (ly > bb[4] ? __fsub_rn(ly, bb[4]) : 0.f);
-    const float dz = lz < bb[2] ? __fsub_rn(bb[2], lz) : (lz > bb[5] ? __fsub_rn(lz, bb[5]) : 0.f);
+    const float dx = slab_d(lx, bb[0], bb[3]);
+    const float dy = slab_d(ly, bb[1], bb[4]);
+    const float dz = slab_d(lz, bb[2], bb[5]);
     return __fadd_rn(__fadd_rn(__fmul_rn(dx, dx), __fmul_rn(dy, dy)), __fmul_rn(dz, dz));
 }
 
@@ -532,6 +580,7 @@ __global__ __launch_bounds__(256) void k_fps_coop(
     constexpr int SCOPE = __HIP_MEMORY_SCOPE_AGENT;
     static_assert(1 + 12 * kK <= kRec && 1 + 12 * kK <= 64 && 1 + 5 * kJ <= kDec && 1 + 5 * kJ <= 128 && kK <= 2,
                   "exchange layout");
+    static_assert(kJ <= 16 && kMaxCpw <= 0x10000, "chunk list entries: slot in 16 bits, landmark mask in 16");
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ float s_pk[kJ][3];       // landmarks to apply
     __shared__ int s_np, s_j, s_abort;
@@ -539,8 +588,8 @@ __global__ __launch_bounds__(256) void k_fps_coop(
     __shared__ uint64_t s_tk[NW][3];
     __shared__ int s_ts[NW][3];
     struct Red {
-        uint64_t key, bound;
-        float x, y, z;
+        uint64_t key;
+        float bound, x, y, z;
     };
     __shared__ Red s_red[2][NW];         // the leader's per-wave reductions (double-buffered)
     __shared__ uint32_t s_pick[kJ][5];   // the leader's picks
@@ -589,34 +638,44 @@ __global__ __launch_bounds__(256) void k_fps_coop(
             __syncthreads();
             for (int s0 = 0; s0 < nmine; s0 += NT) {
                 const int sl = s0 + tid;
-                bool hit = false;
+                uint32_t hitm = 0;  // landmarks that can lower this chunk
                 if (sl < nmine) {
                     const float bb[6] = {s_bb[sl], s_bb[nmine + sl], s_bb[2 * nmine + sl],
                                          s_bb[3 * nmine + sl], s_bb[4 * nmine + sl], s_bb[5 * nmine + sl]};
                     const float km = __uint_as_float((uint32_t)(s_key[sl] >> 32));
 #pragma unroll
                     for (int i = 0; i < kJ; ++i)
-                        if (i < np) hit |= fps_box_d2(lk[i][0], lk[i][1], lk[i][2], bb) < km;
+                        if (i < np) hitm |= (fps_box_d2(lk[i][0], lk[i][1], lk[i][2], bb) < km ? 1u : 0u) << i;
                 }
-                const uint64_t mask = __ballot(hit);
+                const uint64_t mask = __ballot(hitm != 0);
                 uint32_t basep = 0;
                 if (lane == 0 && mask) basep = atomicAdd(&s_n, (uint32_t)__popcll(mask));
                 basep = __shfl(basep, 0, 64);
-                if (hit) s_list[basep + __popcll(mask & ((1ull << lane) - 1ull))] = (uint32_t)sl;
+                if (hitm) s_list[basep + __popcll(mask & ((1ull << lane) - 1ull))] = (uint32_t)sl | (hitm << 16);
             }
             __syncthreads();
             naff = (int)s_n;
         }
-        // 2. update them: running minima, best key and point, second minimum
+        // 2. update them with the landmarks that can lower them (a landmark
+        //    whose box bound is not below the chunk's best minimum leaves every
+        //    running minimum of the chunk as it is): running minima, best key
+        //    and point, second minimum
         for (int e0 = wid * U; e0 < naff; e0 += NW * U) {
             float4 q[8];
             float mm[8];
             int64_t pp[8];
             int sl[U];
+            uint32_t msk[U];
 #pragma unroll
             for (int c = 0; c < U; ++c) {
                 const int ee = e0 + c;
-                sl[c] = ee < naff ? (init ? ee : (int)s_list[ee]) : -1;
+                sl[c] = -1;
+                msk[c] = 0;
+                if (ee < naff) {
+                    const uint32_t w = init ? (uint32_t)ee | (1u << 16) : __builtin_amdgcn_readfirstlane(s_list[ee]);
+                    sl[c] = (int)(w & 0xffffu);
+                    msk[c] = w >> 16;
+                }
             }
 #pragma unroll
             for (int i = 0; i < 8; ++i) {
@@ -639,14 +698,23 @@ __global__ __launch_bounds__(256) void k_fps_coop(
                 float mb = 0.f, m2 = 0.f;  // this lane's best minimum and its second
                 float bx = 0.f, by = 0.f, bz = 0.f;
                 float mn0 = INFINITY, mn1 = INFINITY, mn2 = INFINITY, mx0 = -INFINITY, mx1 = -INFINITY, mx2 = -INFINITY;
+                float d2v[M];
+#pragma unroll
+                for (int u = 0; u < M; ++u) d2v[u] = mm[c * M + u];
+                for (uint32_t mk = msk[c]; mk; mk &= mk - 1u) {
+                    const int t = __builtin_ctz(mk);
+                    const float lx = s_pk[t][0], ly = s_pk[t][1], lz = s_pk[t][2];
+#pragma unroll
+                    for (int u = 0; u < M; ++u) {
+                        const int i = c * M + u;
+                        if (pp[i] >= 0) d2v[u] = fminf(d2v[u], fps_d2(q[i].x, q[i].y, q[i].z, lx, ly, lz));
+                    }
+                }
 #pragma unroll
                 for (int u = 0; u < M; ++u) {
                     const int i = c * M + u;
                     if (pp[i] < 0) continue;
-                    float d2 = mm[i];
-#pragma unroll
-                    for (int t = 0; t < kJ; ++t)
-                        if (t < np) d2 = fminf(d2, fps_d2(q[i].x, q[i].y, q[i].z, lk[t][0], lk[t][1], lk[t][2]));
+                    const float d2 = d2v[u];
                     if (d2 < mm[i]) {
                         mm[i] = d2;
                         mind[pp[i]] = d2;
@@ -668,17 +736,15 @@ __global__ __launch_bounds__(256) void k_fps_coop(
                         mn2 = fminf(mn2, q[i].z); mx2 = fmaxf(mx2, q[i].z);
                     }
                 }
-                const uint64_t km = wave_max_u64(kb);
+                const uint64_t km = wave_max_u64_dpp(kb);
                 const uint64_t own = __ballot(kb == km && kb != 0);
                 const int src = own ? __ffsll((unsigned long long)own) - 1 : 0;
-                bx = __shfl(bx, src, 64);
-                by = __shfl(by, src, 64);
-                bz = __shfl(bz, src, 64);
+                bx = __uint_as_float(rd_lane(__float_as_uint(bx), src));
+                by = __uint_as_float(rd_lane(__float_as_uint(by), src));
+                bz = __uint_as_float(rd_lane(__float_as_uint(bz), src));
                 // second minimum of the chunk: every lane's best except the
                 // chunk's best point, and every lane's second
-                float sec = lane == src ? m2 : fmaxf(mb, m2);
-#pragma unroll
-                for (int o = 32; o > 0; o >>= 1) sec = fmaxf(sec, __shfl_xor(sec, o, 64));
+                const float sec = wave_max_f32_dpp(lane == src ? m2 : fmaxf(mb, m2));
                 if (init) {
 #pragma unroll
                     for (int o = 32; o > 0; o >>= 1) {
@@ -801,14 +867,15 @@ __global__ __launch_bounds__(256) void k_fps_coop(
             int j = 0;
             if (all_in) {
                 for (int p = 0; p < jcap; ++p) {
-                    uint64_t lo = 0, hi = 0;
+                    uint64_t lo = 0;
+                    float hm = 0.f;  // largest running minimum an unpublished point can have
                     int lc = 0;
                     if (w < W) {
-                        hi = key_bound(bw);
+                        hm = bw;
 #pragma unroll
                         for (int c = 0; c < kK; ++c) {
                             if (!valid[c]) continue;
-                            hi = max(hi, key_bound(cb[c]));
+                            hm = fmaxf(hm, cb[c]);
                             const uint64_t k = ((uint64_t)__float_as_uint(cm[c]) << 32) | (uint64_t)(0xffffffffu - cid[c]);
                             if (k > lo) {
                                 lo = k;
@@ -816,31 +883,26 @@ __global__ __launch_bounds__(256) void k_fps_coop(
                             }
                         }
                     }
-                    const uint64_t best = wave_max_u64(lo);
-                    const uint64_t bound = wave_max_u64(hi);
+                    const uint64_t best = wave_max_u64_dpp(lo);
+                    const float bound = wave_max_f32_dpp(hm);
                     const uint64_t own = __ballot(lo == best && lo != 0);
-                    const int src = own ? __ffsll((unsigned long long)own) - 1 : 0;
-                    float px = 0.f, py = 0.f, pz = 0.f;
+                    if (own && lane == __ffsll((unsigned long long)own) - 1) {
 #pragma unroll
-                    for (int c = 0; c < kK; ++c)
-                        if (c == lc) {
-                            px = cxp[c];
-                            py = cyp[c];
-                            pz = czp[c];
-                        }
-                    px = __shfl(px, src, 64);
-                    py = __shfl(py, src, 64);
-                    pz = __shfl(pz, src, 64);
+                        for (int c = 0; c < kK; ++c)
+                            if (c == lc) {
+                                s_red[p & 1][wid].x = cxp[c];
+                                s_red[p & 1][wid].y = cyp[c];
+                                s_red[p & 1][wid].z = czp[c];
+                            }
+                    }
                     if (lane == 0) {
                         s_red[p & 1][wid].key = best;
                         s_red[p & 1][wid].bound = bound;
-                        s_red[p & 1][wid].x = px;
-                        s_red[p & 1][wid].y = py;
-                        s_red[p & 1][wid].z = pz;
                     }
                     __syncthreads();
                     int bwv = 0;
-                    uint64_t gb = s_red[p & 1][0].key, gh = s_red[p & 1][0].bound;
+                    uint64_t gb = s_red[p & 1][0].key;
+                    float gh = s_red[p & 1][0].bound;
 #pragma unroll
                     for (int v = 1; v < NW; ++v) {
                         const uint64_t kv = s_red[p & 1][v].key;
@@ -848,12 +910,12 @@ __global__ __launch_bounds__(256) void k_fps_coop(
                             gb = kv;
                             bwv = v;
                         }
-                        gh = max(gh, s_red[p & 1][v].bound);
+                        gh = fmaxf(gh, s_red[p & 1][v].bound);
                     }
-                    if (p > 0 && !(gb > gh)) break;  // the same decision in every wave
-                    px = s_red[p & 1][bwv].x;
-                    py = s_red[p & 1][bwv].y;
-                    pz = s_red[p & 1][bwv].z;
+                    if (p > 0 && !(gb > key_bound(gh))) break;  // the same decision in every wave
+                    const float px = s_red[p & 1][bwv].x;
+                    const float py = s_red[p & 1][bwv].y;
+                    const float pz = s_red[p & 1][bwv].z;
                     if (tid == 0) {
                         s_pick[p][0] = 0xffffffffu - (uint32_t)gb;
                         s_pick[p][1] = (uint32_t)(gb >> 32);
@@ -920,25 +982,22 @@ __global__ __launch_bounds__(256) void k_fps_coop(
                 s_j = j;
             }
             if (done && j > 0) {
-                auto word = [&](int i) -> uint32_t {
-                    return xw_val(i < 64 ? __shfl(x0, i, 64) : __shfl(x1, i - 64, 64));
-                };
-                for (int p = 0; p < j; ++p) {
-                    const uint32_t pidx = word(1 + 5 * p);
-                    const float pm = __uint_as_float(word(2 + 5 * p));
-                    const float px = __uint_as_float(word(3 + 5 * p));
-                    const float py = __uint_as_float(word(4 + 5 * p));
-                    const float pz = __uint_as_float(word(5 + 5 * p));
+                // word 1 + 5p + f of pick p: f = 0 index, 1 running minimum,
+                // 2..4 coordinates; each lane stores the words it holds
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    const int i = lane + 64 * h;
+                    if (i < 1 || i > 5 * j) continue;
+                    const uint32_t v = xw_val(h ? x1 : x0);
+                    const int p = (i - 1) / 5, f = (i - 1) % 5;
                     const int slot = t_done + p;  // landmark slot this pick decides
-                    if (lane == 0) {
-                        if (slot < a.nl) {
-                            s_pk[p][0] = px;
-                            s_pk[p][1] = py;
-                            s_pk[p][2] = pz;
-                        }
-                        if (wg == 0) {
-                            if (radius) radius[a.lo + slot - 1] = sqrt_rn(pm);
-                            if (slot < a.nl) idx_out[a.lo + slot] = (int32_t)pidx;
+                    if (f >= 2) {
+                        if (slot < a.nl) s_pk[p][f - 2] = __uint_as_float(v);
+                    } else if (wg == 0) {
+                        if (f == 0) {
+                            if (slot < a.nl) idx_out[a.lo + slot] = (int32_t)v;
+                        } else if (radius) {
+                            radius[a.lo + slot - 1] = sqrt_rn(__uint_as_float(v));
                         }
                     }
                 }
