@@ -660,7 +660,7 @@ __global__ __launch_bounds__(256) void k_fps_coop(
         //    whose box bound is not below the chunk's best minimum leaves every
         //    running minimum of the chunk as it is): running minima, best key
         //    and point, second minimum
-        for (int e0 = wid * U; e0 < naff; e0 += NW * U) {
+        for (int e0 = 0; e0 < naff; e0 += NW * U) {  // list entries e0 + c * NW + wid
             float4 q[8];
             float mm[8];
             int64_t pp[8];
@@ -668,7 +668,7 @@ __global__ __launch_bounds__(256) void k_fps_coop(
             uint32_t msk[U];
 #pragma unroll
             for (int c = 0; c < U; ++c) {
-                const int ee = e0 + c;
+                const int ee = e0 + c * NW + wid;
                 sl[c] = -1;
                 msk[c] = 0;
                 if (ee < naff) {
