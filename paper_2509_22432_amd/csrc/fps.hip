@@ -794,7 +794,9 @@ __global__ __launch_bounds__(256) void k_fps_coop(
         }
         __syncthreads();
         const uint32_t id = e + 1;
-        uint64_t *my_rec = rec + ((size_t)(e & 1) * kMaxWG + wg) * kRec;
+        // records word-major: word f of workgroup w at rec[(q * kRec + f) * kMaxWG + w]
+        // (q = exchange parity), so the leader's loads of one word are contiguous
+        uint64_t *my_rec = rec + (size_t)(e & 1) * kRec * kMaxWG + wg;
         if (wid == 0) {
             // 4. the record, one word per lane: bound of the other chunks,
             //    then kK candidates of 12 words
@@ -817,7 +819,7 @@ __global__ __launch_bounds__(256) void k_fps_coop(
                 else if (f == 5) v = __float_as_uint(s_sec[s_]);
                 else v = __float_as_uint(s_bb[(f - 6) * nmine + s_]);
             }
-            if (lane <= 12 * kK) __hip_atomic_store(&my_rec[lane], xw(v, id), __ATOMIC_RELAXED, SCOPE);
+            if (lane <= 12 * kK) __hip_atomic_store(&my_rec[(size_t)lane * kMaxWG], xw(v, id), __ATOMIC_RELAXED, SCOPE);
         }
         uint64_t *my_dec = dec + (size_t)(e & 1) * kDec;
         const int jcap = min(kJ, a.nl + 1 - t_done);
@@ -834,7 +836,7 @@ __global__ __launch_bounds__(256) void k_fps_coop(
 #pragma unroll
                 for (int c = 0; c < kK; ++c) valid[c] = false;
                 if (w < W) {
-                    const uint64_t *rw = rec + ((size_t)(e & 1) * kMaxWG + w) * kRec;
+                    const uint64_t *rw = rec + (size_t)(e & 1) * kRec * kMaxWG + w;
                     const uint64_t w0 = __hip_atomic_load(&rw[0], __ATOMIC_RELAXED, SCOPE);
                     ok &= xw_ok(w0, id);
                     bw = __uint_as_float(xw_val(w0));
@@ -843,7 +845,7 @@ __global__ __launch_bounds__(256) void k_fps_coop(
                         uint32_t v[12];
 #pragma unroll
                         for (int f = 0; f < 12; ++f) {
-                            const uint64_t x = __hip_atomic_load(&rw[1 + 12 * c + f], __ATOMIC_RELAXED, SCOPE);
+                            const uint64_t x = __hip_atomic_load(&rw[(size_t)(1 + 12 * c + f) * kMaxWG], __ATOMIC_RELAXED, SCOPE);
                             ok &= xw_ok(x, id);
                             v[f] = xw_val(x);
                         }
