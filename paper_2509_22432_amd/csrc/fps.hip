@@ -505,6 +505,7 @@ static constexpr int64_t kCoopMin = 1 << 19;      // clouds of at least this man
 static constexpr int kSpinLimit = 1 << 22;        // polls of one exchange before the launch gives up
 static constexpr int kK = 2;                      // candidates a workgroup publishes
 static constexpr int kJ = 16;                     // landmarks decided per exchange, at most
+static constexpr int kT = 16;                     // candidates each leader wave keeps for the replay
 
 struct CoopArgs {
     int32_t b;       // cloud
@@ -580,6 +581,7 @@ __global__ __launch_bounds__(256) void k_fps_coop(
     constexpr int SCOPE = __HIP_MEMORY_SCOPE_AGENT;
     static_assert(1 + 12 * kK <= kRec && 1 + 12 * kK <= 64 && 1 + 5 * kJ <= kDec && 1 + 5 * kJ <= 128 && kK <= 2,
                   "exchange layout");
+    static_assert(NW * kT == 64, "one kept candidate per lane of the replaying wave");
     static_assert(kJ <= 16 && kMaxCpw <= 0x10000, "chunk list entries: slot in 16 bits, landmark mask in 16");
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ float s_pk[kJ][3];       // landmarks to apply
@@ -587,11 +589,12 @@ __global__ __launch_bounds__(256) void k_fps_coop(
     __shared__ uint32_t s_n;
     __shared__ uint64_t s_tk[NW][3];
     __shared__ int s_ts[NW][3];
-    struct Red {
-        uint64_t key;
-        float bound, x, y, z;
+    struct Cand {
+        uint64_t key;                    // 0: no candidate
+        float cb, x, y, z, bb[6];
     };
-    __shared__ Red s_red[2][NW];         // the leader's per-wave reductions (double-buffered)
+    __shared__ Cand s_cand[NW * kT];     // the leader's kept candidates
+    __shared__ float s_bnd[NW];          // bound of the candidates each wave did not keep
     __shared__ uint32_t s_pick[kJ][5];   // the leader's picks
     __shared__ int s_wok[NW];
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
@@ -864,74 +867,83 @@ __global__ __launch_bounds__(256) void k_fps_coop(
                 if (!done) __builtin_amdgcn_s_sleep(1);
             }
             if (lane == 0) s_wok[wid] = done ? 1 : 0;
+            {
+                // every wave keeps its kT best candidates (keys above theta,
+                // the (kT + 1)-th largest key it holds, found bit by bit);
+                // the points of every other chunk it holds have running
+                // minima of at most max(theta's minimum, the next-chunk
+                // bounds), since a chunk's second minimum never exceeds its best
+                uint64_t k[kK];
+#pragma unroll
+                for (int c = 0; c < kK; ++c)
+                    k[c] = (w < W && valid[c]) ? ((uint64_t)__float_as_uint(cm[c]) << 32) | (uint64_t)(0xffffffffu - cid[c]) : 0;
+                uint64_t th = 0;
+                for (int bit = 63; bit >= 0; --bit) {
+                    const uint64_t t = th | (1ull << bit);
+                    int cnt = 0;
+#pragma unroll
+                    for (int c = 0; c < kK; ++c) cnt += __popcll(__ballot(k[c] >= t));
+                    if (cnt > kT) th = t;
+                }
+                const uint64_t below = (1ull << lane) - 1ull;
+                int base = 0;
+#pragma unroll
+                for (int c = 0; c < kK; ++c) {
+                    const bool in = k[c] > th;
+                    const uint64_t m = __ballot(in);
+                    if (in) {
+                        Cand &o = s_cand[wid * kT + base + __popcll(m & below)];
+                        o.key = k[c];
+                        o.cb = cb[c];
+                        o.x = cxp[c];
+                        o.y = cyp[c];
+                        o.z = czp[c];
+#pragma unroll
+                        for (int f = 0; f < 6; ++f) o.bb[f] = cbb[c][f];
+                    }
+                    base += __popcll(m);
+                }
+                if (lane >= base && lane < kT) s_cand[wid * kT + lane].key = 0;
+                const float bmax = wave_max_f32_dpp(w < W ? bw : 0.f);
+                if (lane == 0) s_bnd[wid] = fmaxf(bmax, __uint_as_float((uint32_t)(th >> 32)));
+            }
             __syncthreads();
             const bool all_in = s_wok[0] && s_wok[1] && s_wok[2] && s_wok[3];
             int j = 0;
-            if (all_in) {
+            if (all_in && wid == 0) {
+                // one wave replays the greedy rule on the NW * kT kept
+                // candidates, one per lane
+                const Cand &o = s_cand[lane];
+                const bool alive = o.key != 0;
+                float m = __uint_as_float((uint32_t)(o.key >> 32)), b = o.cb;
+                const uint32_t lid = 0xffffffffu - (uint32_t)o.key;
+                const float x = o.x, y = o.y, z = o.z;
+                float bb[6];
+#pragma unroll
+                for (int f = 0; f < 6; ++f) bb[f] = o.bb[f];
+                const float b0 = fmaxf(fmaxf(s_bnd[0], s_bnd[1]), fmaxf(s_bnd[2], s_bnd[3]));
                 for (int p = 0; p < jcap; ++p) {
-                    uint64_t lo = 0;
-                    float hm = 0.f;  // largest running minimum an unpublished point can have
-                    int lc = 0;
-                    if (w < W) {
-                        hm = bw;
-#pragma unroll
-                        for (int c = 0; c < kK; ++c) {
-                            if (!valid[c]) continue;
-                            hm = fmaxf(hm, cb[c]);
-                            const uint64_t k = ((uint64_t)__float_as_uint(cm[c]) << 32) | (uint64_t)(0xffffffffu - cid[c]);
-                            if (k > lo) {
-                                lo = k;
-                                lc = c;
-                            }
-                        }
-                    }
+                    const uint64_t lo = alive ? ((uint64_t)__float_as_uint(m) << 32) | (uint64_t)(0xffffffffu - lid) : 0;
                     const uint64_t best = wave_max_u64_dpp(lo);
-                    const float bound = wave_max_f32_dpp(hm);
+                    const float gh = fmaxf(b0, wave_max_f32_dpp(alive ? b : 0.f));
+                    if (p > 0 && !(best > key_bound(gh))) break;
                     const uint64_t own = __ballot(lo == best && lo != 0);
-                    if (own && lane == __ffsll((unsigned long long)own) - 1) {
-#pragma unroll
-                        for (int c = 0; c < kK; ++c)
-                            if (c == lc) {
-                                s_red[p & 1][wid].x = cxp[c];
-                                s_red[p & 1][wid].y = cyp[c];
-                                s_red[p & 1][wid].z = czp[c];
-                            }
-                    }
+                    const int src = own ? __ffsll((unsigned long long)own) - 1 : 0;
+                    const float px = __uint_as_float(rd_lane(__float_as_uint(x), src));
+                    const float py = __uint_as_float(rd_lane(__float_as_uint(y), src));
+                    const float pz = __uint_as_float(rd_lane(__float_as_uint(z), src));
                     if (lane == 0) {
-                        s_red[p & 1][wid].key = best;
-                        s_red[p & 1][wid].bound = bound;
-                    }
-                    __syncthreads();
-                    int bwv = 0;
-                    uint64_t gb = s_red[p & 1][0].key;
-                    float gh = s_red[p & 1][0].bound;
-#pragma unroll
-                    for (int v = 1; v < NW; ++v) {
-                        const uint64_t kv = s_red[p & 1][v].key;
-                        if (kv > gb) {
-                            gb = kv;
-                            bwv = v;
-                        }
-                        gh = fmaxf(gh, s_red[p & 1][v].bound);
-                    }
-                    if (p > 0 && !(gb > key_bound(gh))) break;  // the same decision in every wave
-                    const float px = s_red[p & 1][bwv].x;
-                    const float py = s_red[p & 1][bwv].y;
-                    const float pz = s_red[p & 1][bwv].z;
-                    if (tid == 0) {
-                        s_pick[p][0] = 0xffffffffu - (uint32_t)gb;
-                        s_pick[p][1] = (uint32_t)(gb >> 32);
+                        s_pick[p][0] = 0xffffffffu - (uint32_t)best;
+                        s_pick[p][1] = (uint32_t)(best >> 32);
                         s_pick[p][2] = __float_as_uint(px);
                         s_pick[p][3] = __float_as_uint(py);
                         s_pick[p][4] = __float_as_uint(pz);
                     }
                     ++j;
-                    // the candidates and the chunk bounds after this pick
-#pragma unroll
-                    for (int c = 0; c < kK; ++c) {
-                        if (!valid[c]) continue;
-                        cm[c] = fminf(cm[c], fps_d2(cxp[c], cyp[c], czp[c], px, py, pz));
-                        cb[c] = fminf(cb[c], fps_box_far_d2(px, py, pz, cbb[c]));
+                    // the candidate and its chunk's bound after this pick
+                    if (alive) {
+                        m = fminf(m, fps_d2(x, y, z, px, py, pz));
+                        b = fminf(b, fps_box_far_d2(px, py, pz, bb));
                     }
                 }
             }
