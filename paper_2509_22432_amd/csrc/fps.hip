@@ -33,7 +33,7 @@ static constexpr int kU = 8;           // points per thread per step
 static constexpr int kMaxDim = 1024;   // cells per axis of a row grid (slab keys fit in LDS)
 static constexpr int kMaxWG = 256;     // workgroups of one cooperative launch
 static constexpr int kRec = 32;        // 64-bit words of a workgroup's record in an exchange
-static constexpr int kDec = 96;        // 64-bit words of an exchange's decision
+static constexpr int kDec = 192;       // 64-bit words of an exchange's decision
 
 struct FpsState {
     int32_t cur;  // local index of the newest landmark
@@ -500,11 +500,11 @@ __global__ __launch_bounds__(kPT) void k_fps_persist(
 // landmarks.  Exchanged words carry the exchange number, so a stale word is
 // never taken for a fresh one.
 
-static constexpr int kMaxCpw = 2816;              // chunk slots per workgroup (52 B of LDS each)
+static constexpr int kMaxCpw = 2688;              // chunk slots per workgroup (56 B of LDS each)
 static constexpr int64_t kCoopMin = 1 << 19;      // clouds of at least this many points
 static constexpr int kSpinLimit = 1 << 22;        // polls of one exchange before the launch gives up
 static constexpr int kK = 2;                      // candidates a workgroup publishes
-static constexpr int kJ = 16;                     // landmarks decided per exchange, at most
+static constexpr int kJ = 32;                     // landmarks decided per exchange, at most
 static constexpr int kT = 16;                     // candidates each leader wave keeps for the replay
 
 struct CoopArgs {
@@ -579,10 +579,11 @@ __global__ __launch_bounds__(256) void k_fps_coop(
     constexpr int M = 1 << LM;          // points per lane per chunk
     constexpr int U = 8 >> LM;          // chunks per wave step
     constexpr int SCOPE = __HIP_MEMORY_SCOPE_AGENT;
-    static_assert(1 + 12 * kK <= kRec && 1 + 12 * kK <= 64 && 1 + 5 * kJ <= kDec && 1 + 5 * kJ <= 128 && kK <= 2,
+    constexpr int DH = (1 + 5 * kJ + 63) / 64;  // decision words a lane reads
+    static_assert(1 + 12 * kK <= kRec && 1 + 12 * kK <= 64 && 1 + 5 * kJ <= kDec && kDec <= 64 * DH && kK <= 2,
                   "exchange layout");
     static_assert(NW * kT == 64, "one kept candidate per lane of the replaying wave");
-    static_assert(kJ <= 16 && kMaxCpw <= 0x10000, "chunk list entries: slot in 16 bits, landmark mask in 16");
+    static_assert(kJ <= 32, "landmark masks of 32 bits");
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ float s_pk[kJ][3];       // landmarks to apply
     __shared__ int s_np, s_j, s_abort;
@@ -606,7 +607,8 @@ __global__ __launch_bounds__(256) void k_fps_coop(
     float *s_bb = (float *)(s_key + nmine);
     float *s_px = s_bb + 6 * nmine;
     float *s_sec = s_px + 3 * nmine;
-    uint32_t *s_list = (uint32_t *)(s_sec + nmine);
+    uint32_t *s_list = (uint32_t *)(s_sec + nmine);  // listed chunk slots
+    uint32_t *s_lmask = s_list + nmine;               // and the landmarks that can lower them
 
     const GridParam g = gp[a.b];
     const int64_t pb = g.pt_base, npts = g.npts;
@@ -625,13 +627,6 @@ __global__ __launch_bounds__(256) void k_fps_coop(
     for (uint32_t e = 0;; ++e) {
         const bool init = e == 0;
         const int np = s_np;
-        float lk[kJ][3];
-#pragma unroll
-        for (int i = 0; i < kJ; ++i) {
-            lk[i][0] = i < np ? s_pk[i][0] : 0.f;
-            lk[i][1] = i < np ? s_pk[i][1] : 0.f;
-            lk[i][2] = i < np ? s_pk[i][2] : 0.f;
-        }
         // 1. the chunks some landmark can lower (all of them at first)
         int naff;
         if (init) {
@@ -646,15 +641,23 @@ __global__ __launch_bounds__(256) void k_fps_coop(
                     const float bb[6] = {s_bb[sl], s_bb[nmine + sl], s_bb[2 * nmine + sl],
                                          s_bb[3 * nmine + sl], s_bb[4 * nmine + sl], s_bb[5 * nmine + sl]};
                     const float km = __uint_as_float((uint32_t)(s_key[sl] >> 32));
+                    for (int t0 = 0; t0 < np; t0 += 8) {
 #pragma unroll
-                    for (int i = 0; i < kJ; ++i)
-                        if (i < np) hitm |= (fps_box_d2(lk[i][0], lk[i][1], lk[i][2], bb) < km ? 1u : 0u) << i;
+                        for (int i = 0; i < 8; ++i) {
+                            const int t = t0 + i;
+                            if (t < np) hitm |= (fps_box_d2(s_pk[t][0], s_pk[t][1], s_pk[t][2], bb) < km ? 1u : 0u) << t;
+                        }
+                    }
                 }
                 const uint64_t mask = __ballot(hitm != 0);
                 uint32_t basep = 0;
                 if (lane == 0 && mask) basep = atomicAdd(&s_n, (uint32_t)__popcll(mask));
                 basep = __shfl(basep, 0, 64);
-                if (hitm) s_list[basep + __popcll(mask & ((1ull << lane) - 1ull))] = (uint32_t)sl | (hitm << 16);
+                if (hitm) {
+                    const uint32_t at = basep + __popcll(mask & ((1ull << lane) - 1ull));
+                    s_list[at] = (uint32_t)sl;
+                    s_lmask[at] = hitm;
+                }
             }
             __syncthreads();
             naff = (int)s_n;
@@ -675,9 +678,8 @@ __global__ __launch_bounds__(256) void k_fps_coop(
                 sl[c] = -1;
                 msk[c] = 0;
                 if (ee < naff) {
-                    const uint32_t w = init ? (uint32_t)ee | (1u << 16) : __builtin_amdgcn_readfirstlane(s_list[ee]);
-                    sl[c] = (int)(w & 0xffffu);
-                    msk[c] = w >> 16;
+                    sl[c] = init ? ee : (int)__builtin_amdgcn_readfirstlane(s_list[ee]);
+                    msk[c] = init ? 1u : __builtin_amdgcn_readfirstlane(s_lmask[ee]);
                 }
             }
 #pragma unroll
@@ -957,7 +959,7 @@ __global__ __launch_bounds__(256) void k_fps_coop(
                     }
                 } else {
 #pragma unroll
-                    for (int h = 0; h < 2; ++h) {
+                    for (int h = 0; h < DH; ++h) {
                         const int i = lane + 64 * h;
                         if (i > 5 * j) continue;
                         const uint32_t v = i == 0 ? (uint32_t)j : s_pick[(i - 1) / 5][(i - 1) % 5];
@@ -966,20 +968,25 @@ __global__ __launch_bounds__(256) void k_fps_coop(
                 }
             }
         }
-        // 6. every workgroup reads the decision (words lane and lane + 64)
+        // 6. every workgroup reads the decision (words lane + 64 h)
         if (wid == 0) {
-            uint64_t x0 = 0, x1 = 0;
+            uint64_t x[DH];
             bool done = false;
             int j = 0;
             for (int spin = 0; spin < kSpinLimit; ++spin) {
-                x0 = __hip_atomic_load(&my_dec[lane], __ATOMIC_RELAXED, SCOPE);
-                x1 = lane + 64 <= 5 * kJ ? __hip_atomic_load(&my_dec[lane + 64], __ATOMIC_RELAXED, SCOPE) : 0;
-                const uint64_t w0 = __shfl(x0, 0, 64);
+#pragma unroll
+                for (int h = 0; h < DH; ++h)
+                    x[h] = lane + 64 * h <= 5 * kJ ? __hip_atomic_load(&my_dec[lane + 64 * h], __ATOMIC_RELAXED, SCOPE) : 0;
+                const uint64_t w0 = __shfl(x[0], 0, 64);
                 if (xw_ok(w0, id)) {
                     j = (int)xw_val(w0);
-                    const bool ok0 = !(lane >= 1 && lane <= 5 * j) || xw_ok(x0, id);
-                    const bool ok1 = !(lane + 64 <= 5 * j) || xw_ok(x1, id);
-                    if (__all(ok0 && ok1)) {
+                    bool ok = true;
+#pragma unroll
+                    for (int h = 0; h < DH; ++h) {
+                        const int i = lane + 64 * h;
+                        ok &= !(i >= 1 && i <= 5 * j) || xw_ok(x[h], id);
+                    }
+                    if (__all(ok)) {
                         done = true;
                         break;
                     }
@@ -999,10 +1006,10 @@ __global__ __launch_bounds__(256) void k_fps_coop(
                 // word 1 + 5p + f of pick p: f = 0 index, 1 running minimum,
                 // 2..4 coordinates; each lane stores the words it holds
 #pragma unroll
-                for (int h = 0; h < 2; ++h) {
+                for (int h = 0; h < DH; ++h) {
                     const int i = lane + 64 * h;
                     if (i < 1 || i > 5 * j) continue;
-                    const uint32_t v = xw_val(h ? x1 : x0);
+                    const uint32_t v = xw_val(x[h]);
                     const int p = (i - 1) / 5, f = (i - 1) % 5;
                     const int slot = t_done + p;  // landmark slot this pick decides
                     if (f >= 2) {
@@ -1063,7 +1070,7 @@ static bool coop_shape(int64_t n, int cus, CoopShape *cs) {
             cs->nwg = (int32_t)w;
             cs->lm = l;
             cs->nchunk = nc;
-            cs->shmem = (int)(cpw * 52);
+            cs->shmem = (int)(cpw * 56);
             return true;
         }
     }
