@@ -101,27 +101,21 @@ __device__ __forceinline__ uint32_t dpp_mov(uint32_t v) {
 __device__ __forceinline__ uint32_t rd_lane(uint32_t v, int l) { return (uint32_t)__builtin_amdgcn_readlane((int)v, l); }
 
 template <int CTRL>
-__device__ __forceinline__ void dpp_max_step(uint32_t &hi, uint32_t &lo) {
-    const uint32_t h = dpp_mov<CTRL>(hi), l = dpp_mov<CTRL>(lo);
-    const bool take = h > hi || (h == hi && l > lo);
-    hi = take ? h : hi;
-    lo = take ? l : lo;
-}
+__device__ __forceinline__ uint32_t dpp_max_u32(uint32_t v) { return max(v, dpp_mov<CTRL>(v)); }
+template <int CTRL>
+__device__ __forceinline__ uint32_t dpp_min_u32(uint32_t v) { return min(v, dpp_mov<CTRL>(v)); }
 
-// wave-wide maximum, the same in every lane (all 64 lanes active)
-__device__ __forceinline__ uint64_t wave_max_u64_dpp(uint64_t v) {
-    uint32_t hi = (uint32_t)(v >> 32), lo = (uint32_t)v;
-    dpp_max_step<0xb1>(hi, lo);
-    dpp_max_step<0x4e>(hi, lo);
-    dpp_max_step<0x141>(hi, lo);
-    dpp_max_step<0x140>(hi, lo);
-    uint64_t r = ((uint64_t)rd_lane(hi, 0) << 32) | rd_lane(lo, 0);
-#pragma unroll
-    for (int row = 16; row < 64; row += 16) {
-        const uint64_t x = ((uint64_t)rd_lane(hi, row) << 32) | rd_lane(lo, row);
-        r = x > r ? x : r;
-    }
-    return r;
+// the lane holding the wave's largest key (mb << 32) | ~id: the largest mb,
+// and among equal mb the lowest id (all 64 lanes active); mmax gets that mb
+__device__ __forceinline__ int wave_argmax_key(uint32_t mb, uint32_t id, uint32_t &mmax) {
+    uint32_t v = dpp_max_u32<0x140>(dpp_max_u32<0x141>(dpp_max_u32<0x4e>(dpp_max_u32<0xb1>(mb))));
+    mmax = max(max(rd_lane(v, 0), rd_lane(v, 16)), max(rd_lane(v, 32), rd_lane(v, 48)));
+    const uint64_t tied = __ballot(mb == mmax);
+    if (__popcll(tied) == 1) return __ffsll((unsigned long long)tied) - 1;
+    uint32_t u = mb == mmax ? id : 0xffffffffu;
+    u = dpp_min_u32<0x140>(dpp_min_u32<0x141>(dpp_min_u32<0x4e>(dpp_min_u32<0xb1>(u))));
+    const uint32_t umin = min(min(rd_lane(u, 0), rd_lane(u, 16)), min(rd_lane(u, 32), rd_lane(u, 48)));
+    return __ffsll((unsigned long long)__ballot(mb == mmax && id == umin)) - 1;
 }
 
 __device__ __forceinline__ float wave_max_f32_dpp(float v) {
@@ -741,9 +735,9 @@ __global__ __launch_bounds__(256) void k_fps_coop(
                         mn2 = fminf(mn2, q[i].z); mx2 = fmaxf(mx2, q[i].z);
                     }
                 }
-                const uint64_t km = wave_max_u64_dpp(kb);
-                const uint64_t own = __ballot(kb == km && kb != 0);
-                const int src = own ? __ffsll((unsigned long long)own) - 1 : 0;
+                uint32_t kmb;
+                const int src = wave_argmax_key((uint32_t)(kb >> 32), 0xffffffffu - (uint32_t)kb, kmb);
+                const uint64_t km = ((uint64_t)kmb << 32) | rd_lane((uint32_t)kb, src);
                 bx = __uint_as_float(rd_lane(__float_as_uint(bx), src));
                 by = __uint_as_float(rd_lane(__float_as_uint(by), src));
                 bz = __uint_as_float(rd_lane(__float_as_uint(bz), src));
@@ -778,24 +772,26 @@ __global__ __launch_bounds__(256) void k_fps_coop(
             uint64_t tk[3] = {0, 0, 0};
             int ts[3] = {-1, -1, -1};
             for (int sl = tid; sl < nmine; sl += NT) top3_insert(tk, ts, s_key[sl], sl);
+            // the wave's three best: take the best lane head three times
 #pragma unroll
-            for (int o = 32; o > 0; o >>= 1) {
-                uint64_t ok[3];
-                int os[3];
-#pragma unroll
-                for (int r = 0; r < 3; ++r) {
-                    ok[r] = __shfl_xor(tk[r], o, 64);
-                    os[r] = __shfl_xor(ts[r], o, 64);
+            for (int r = 0; r < 3; ++r) {
+                uint32_t hb;
+                const int src = wave_argmax_key((uint32_t)(tk[0] >> 32), 0xffffffffu - (uint32_t)tk[0], hb);
+                const uint64_t kw = ((uint64_t)hb << 32) | rd_lane((uint32_t)tk[0], src);
+                const int sw = (int)rd_lane((uint32_t)ts[0], src);
+                if (lane == 0) {
+                    s_tk[wid][r] = kw;
+                    s_ts[wid][r] = kw ? sw : -1;
                 }
-#pragma unroll
-                for (int r = 0; r < 3; ++r) top3_insert(tk, ts, ok[r], os[r]);
+                if (lane == src) {
+                    tk[0] = tk[1];
+                    ts[0] = ts[1];
+                    tk[1] = tk[2];
+                    ts[1] = ts[2];
+                    tk[2] = 0;
+                    ts[2] = -1;
+                }
             }
-            if (lane == 0)
-#pragma unroll
-                for (int r = 0; r < 3; ++r) {
-                    s_tk[wid][r] = tk[r];
-                    s_ts[wid][r] = ts[r];
-                }
         }
         __syncthreads();
         const uint32_t id = e + 1;
@@ -925,12 +921,11 @@ __global__ __launch_bounds__(256) void k_fps_coop(
                 for (int f = 0; f < 6; ++f) bb[f] = o.bb[f];
                 const float b0 = fmaxf(fmaxf(s_bnd[0], s_bnd[1]), fmaxf(s_bnd[2], s_bnd[3]));
                 for (int p = 0; p < jcap; ++p) {
-                    const uint64_t lo = alive ? ((uint64_t)__float_as_uint(m) << 32) | (uint64_t)(0xffffffffu - lid) : 0;
-                    const uint64_t best = wave_max_u64_dpp(lo);
+                    uint32_t mmax;
+                    const int src = wave_argmax_key(alive ? __float_as_uint(m) : 0u, alive ? lid : 0xffffffffu, mmax);
+                    const uint64_t best = ((uint64_t)mmax << 32) | (0xffffffffu - rd_lane(alive ? lid : 0xffffffffu, src));
                     const float gh = fmaxf(b0, wave_max_f32_dpp(alive ? b : 0.f));
                     if (p > 0 && !(best > key_bound(gh))) break;
-                    const uint64_t own = __ballot(lo == best && lo != 0);
-                    const int src = own ? __ffsll((unsigned long long)own) - 1 : 0;
                     const float px = __uint_as_float(rd_lane(__float_as_uint(x), src));
                     const float py = __uint_as_float(rd_lane(__float_as_uint(y), src));
                     const float pz = __uint_as_float(rd_lane(__float_as_uint(z), src));
