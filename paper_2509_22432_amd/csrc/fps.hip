@@ -494,7 +494,8 @@ __global__ __launch_bounds__(kPT) void k_fps_persist(
 // landmarks.  Exchanged words carry the exchange number, so a stale word is
 // never taken for a fresh one.
 
-static constexpr int kMaxCpw = 2688;              // chunk slots per workgroup (56 B of LDS each)
+static constexpr int kMaxCpw = 2560;              // chunk slots per workgroup (60 B of LDS each)
+static constexpr int kG = 8;                      // consecutive chunk slots of a workgroup under one group bound
 static constexpr int64_t kCoopMin = 1 << 19;      // clouds of at least this many points
 static constexpr int kSpinLimit = 1 << 22;        // polls of one exchange before the launch gives up
 static constexpr int kK = 2;                      // candidates a workgroup publishes
@@ -576,7 +577,7 @@ __global__ __launch_bounds__(256) void k_fps_coop(
     constexpr int DH = (1 + 5 * kJ + 63) / 64;  // decision words a lane reads
     static_assert(1 + 12 * kK <= kRec && 1 + 12 * kK <= 64 && 1 + 5 * kJ <= kDec && kDec <= 64 * DH && kK <= 2,
                   "exchange layout");
-    static_assert(NW * kT == 64, "one kept candidate per lane of the replaying wave");
+    static_assert(NW * kT % 64 == 0 && kT <= 64, "whole kept candidates per lane of the replaying wave");
     static_assert(kJ <= 32, "landmark masks of 32 bits");
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ float s_pk[kJ][3];       // landmarks to apply
@@ -603,6 +604,10 @@ __global__ __launch_bounds__(256) void k_fps_coop(
     float *s_sec = s_px + 3 * nmine;
     uint32_t *s_list = (uint32_t *)(s_sec + nmine);  // listed chunk slots
     uint32_t *s_lmask = s_list + nmine;               // and the landmarks that can lower them
+    const int ngrp = (nmine + kG - 1) / kG;           // groups of kG slots (slot order is Morton order)
+    float *s_gbb = (float *)(s_lmask + nmine);        // group boxes (union of the slot boxes)
+    float *s_gkm = s_gbb + 6 * ngrp;                  // group best minima (largest slot minimum)
+    uint32_t *s_gmask = (uint32_t *)(s_gkm + ngrp);   // landmarks that can reach a group
 
     const GridParam g = gp[a.b];
     const int64_t pb = g.pt_base, npts = g.npts;
@@ -627,20 +632,35 @@ __global__ __launch_bounds__(256) void k_fps_coop(
             naff = nmine;
         } else {
             if (tid == 0) s_n = 0;
+            // a) landmarks against group bounds: a landmark whose distance
+            //    bound to a group box is not below the group's best minimum
+            //    cannot lower any of its chunks (a slot box lies inside the
+            //    group box, and the bound only grows as the box shrinks);
+            //    q threads per group split the landmarks
+            const int q = max(1, NT / ngrp);
+            for (int u = tid; u < ngrp * q; u += NT) {
+                const int gi = u / q, r = u - gi * q;
+                const float gb[6] = {s_gbb[gi], s_gbb[ngrp + gi], s_gbb[2 * ngrp + gi],
+                                     s_gbb[3 * ngrp + gi], s_gbb[4 * ngrp + gi], s_gbb[5 * ngrp + gi]};
+                const float gkm = s_gkm[gi];
+                uint32_t gm = 0;
+                for (int t = r; t < np; t += q)
+                    gm |= (fps_box_d2(s_pk[t][0], s_pk[t][1], s_pk[t][2], gb) < gkm ? 1u : 0u) << t;
+                if (gm) atomicOr(&s_gmask[gi], gm);
+            }
             __syncthreads();
+            // b) the slots of reached groups against those landmarks
             for (int s0 = 0; s0 < nmine; s0 += NT) {
                 const int sl = s0 + tid;
                 uint32_t hitm = 0;  // landmarks that can lower this chunk
-                if (sl < nmine) {
+                const uint32_t gm = sl < nmine ? s_gmask[sl / kG] : 0u;
+                if (gm) {
                     const float bb[6] = {s_bb[sl], s_bb[nmine + sl], s_bb[2 * nmine + sl],
                                          s_bb[3 * nmine + sl], s_bb[4 * nmine + sl], s_bb[5 * nmine + sl]};
                     const float km = __uint_as_float((uint32_t)(s_key[sl] >> 32));
-                    for (int t0 = 0; t0 < np; t0 += 8) {
-#pragma unroll
-                        for (int i = 0; i < 8; ++i) {
-                            const int t = t0 + i;
-                            if (t < np) hitm |= (fps_box_d2(s_pk[t][0], s_pk[t][1], s_pk[t][2], bb) < km ? 1u : 0u) << t;
-                        }
+                    for (uint32_t mk = gm; mk; mk &= mk - 1u) {
+                        const int t = __builtin_ctz(mk);
+                        hitm |= (fps_box_d2(s_pk[t][0], s_pk[t][1], s_pk[t][2], bb) < km ? 1u : 0u) << t;
                     }
                 }
                 const uint64_t mask = __ballot(hitm != 0);
@@ -655,6 +675,7 @@ __global__ __launch_bounds__(256) void k_fps_coop(
             }
             __syncthreads();
             naff = (int)s_n;
+            for (int gi = tid; gi < ngrp; gi += NT) s_gmask[gi] = 0u;  // read again only after later barriers
         }
         // 2. update them with the landmarks that can lower them (a landmark
         //    whose box bound is not below the chunk's best minimum leaves every
@@ -767,6 +788,25 @@ __global__ __launch_bounds__(256) void k_fps_coop(
             }
         }
         __syncthreads();
+        // group bounds: the boxes once, the best minima after every update
+        for (int gi = tid; gi < ngrp; gi += NT) {
+            const int s_lo = gi * kG, s_hi = min(nmine, s_lo + kG);
+            float gkm = 0.f;
+            for (int sl = s_lo; sl < s_hi; ++sl) gkm = fmaxf(gkm, __uint_as_float((uint32_t)(s_key[sl] >> 32)));
+            s_gkm[gi] = gkm;
+            if (init) {
+                for (int f = 0; f < 3; ++f) {
+                    float lo = INFINITY, hi = -INFINITY;
+                    for (int sl = s_lo; sl < s_hi; ++sl) {
+                        lo = fminf(lo, s_bb[f * nmine + sl]);
+                        hi = fmaxf(hi, s_bb[(3 + f) * nmine + sl]);
+                    }
+                    s_gbb[f * ngrp + gi] = lo;
+                    s_gbb[(3 + f) * ngrp + gi] = hi;
+                }
+                s_gmask[gi] = 0u;
+            }
+        }
         // 3. this workgroup's three best chunks
         {
             uint64_t tk[3] = {0, 0, 0};
@@ -910,25 +950,50 @@ __global__ __launch_bounds__(256) void k_fps_coop(
             int j = 0;
             if (all_in && wid == 0) {
                 // one wave replays the greedy rule on the NW * kT kept
-                // candidates, one per lane
-                const Cand &o = s_cand[lane];
-                const bool alive = o.key != 0;
-                float m = __uint_as_float((uint32_t)(o.key >> 32)), b = o.cb;
-                const uint32_t lid = 0xffffffffu - (uint32_t)o.key;
-                const float x = o.x, y = o.y, z = o.z;
-                float bb[6];
+                // candidates, kR per lane
+                constexpr int kR = NW * kT / 64;
+                bool alive[kR];
+                float m[kR], b[kR], x[kR], y[kR], z[kR], bb[kR][6];
+                uint32_t lid[kR];
 #pragma unroll
-                for (int f = 0; f < 6; ++f) bb[f] = o.bb[f];
+                for (int r = 0; r < kR; ++r) {
+                    const Cand &o = s_cand[lane + 64 * r];
+                    alive[r] = o.key != 0;
+                    m[r] = __uint_as_float((uint32_t)(o.key >> 32));
+                    b[r] = o.cb;
+                    lid[r] = 0xffffffffu - (uint32_t)o.key;
+                    x[r] = o.x;
+                    y[r] = o.y;
+                    z[r] = o.z;
+#pragma unroll
+                    for (int f = 0; f < 6; ++f) bb[r][f] = o.bb[f];
+                }
                 const float b0 = fmaxf(fmaxf(s_bnd[0], s_bnd[1]), fmaxf(s_bnd[2], s_bnd[3]));
                 for (int p = 0; p < jcap; ++p) {
+                    // this lane's best candidate (largest minimum, then lowest index)
+                    uint32_t mb = alive[0] ? __float_as_uint(m[0]) : 0u, ib = alive[0] ? lid[0] : 0xffffffffu;
+                    float hb = alive[0] ? b[0] : 0.f, bx = x[0], by = y[0], bz = z[0];
+#pragma unroll
+                    for (int r = 1; r < kR; ++r) {
+                        if (!alive[r]) continue;
+                        const uint32_t mr = __float_as_uint(m[r]);
+                        if (mr > mb || (mr == mb && lid[r] < ib)) {
+                            mb = mr;
+                            ib = lid[r];
+                            bx = x[r];
+                            by = y[r];
+                            bz = z[r];
+                        }
+                        hb = fmaxf(hb, b[r]);
+                    }
                     uint32_t mmax;
-                    const int src = wave_argmax_key(alive ? __float_as_uint(m) : 0u, alive ? lid : 0xffffffffu, mmax);
-                    const uint64_t best = ((uint64_t)mmax << 32) | (0xffffffffu - rd_lane(alive ? lid : 0xffffffffu, src));
-                    const float gh = fmaxf(b0, wave_max_f32_dpp(alive ? b : 0.f));
+                    const int src = wave_argmax_key(mb, ib, mmax);
+                    const uint64_t best = ((uint64_t)mmax << 32) | (0xffffffffu - rd_lane(ib, src));
+                    const float gh = fmaxf(b0, wave_max_f32_dpp(hb));
                     if (p > 0 && !(best > key_bound(gh))) break;
-                    const float px = __uint_as_float(rd_lane(__float_as_uint(x), src));
-                    const float py = __uint_as_float(rd_lane(__float_as_uint(y), src));
-                    const float pz = __uint_as_float(rd_lane(__float_as_uint(z), src));
+                    const float px = __uint_as_float(rd_lane(__float_as_uint(bx), src));
+                    const float py = __uint_as_float(rd_lane(__float_as_uint(by), src));
+                    const float pz = __uint_as_float(rd_lane(__float_as_uint(bz), src));
                     if (lane == 0) {
                         s_pick[p][0] = 0xffffffffu - (uint32_t)best;
                         s_pick[p][1] = (uint32_t)(best >> 32);
@@ -937,10 +1002,12 @@ __global__ __launch_bounds__(256) void k_fps_coop(
                         s_pick[p][4] = __float_as_uint(pz);
                     }
                     ++j;
-                    // the candidate and its chunk's bound after this pick
-                    if (alive) {
-                        m = fminf(m, fps_d2(x, y, z, px, py, pz));
-                        b = fminf(b, fps_box_far_d2(px, py, pz, bb));
+                    // the candidates and their chunks' bounds after this pick
+#pragma unroll
+                    for (int r = 0; r < kR; ++r) {
+                        if (!alive[r]) continue;
+                        m[r] = fminf(m[r], fps_d2(x[r], y[r], z[r], px, py, pz));
+                        b[r] = fminf(b[r], fps_box_far_d2(px, py, pz, bb[r]));
                     }
                 }
             }
@@ -1065,7 +1132,7 @@ static bool coop_shape(int64_t n, int cus, CoopShape *cs) {
             cs->nwg = (int32_t)w;
             cs->lm = l;
             cs->nchunk = nc;
-            cs->shmem = (int)(cpw * 56);
+            cs->shmem = (int)(cpw * 56 + (cpw + kG - 1) / kG * 32);
             return true;
         }
     }
