@@ -906,28 +906,38 @@ __global__ __launch_bounds__(256) void k_fps_coop(
             }
             if (lane == 0) s_wok[wid] = done ? 1 : 0;
             {
-                // every wave keeps its kT best candidates (keys above theta,
-                // the (kT + 1)-th largest key it holds, found bit by bit);
-                // the points of every other chunk it holds have running
-                // minima of at most max(theta's minimum, the next-chunk
-                // bounds), since a chunk's second minimum never exceeds its best
+                // every wave keeps its best key and the candidates whose
+                // minimum exceeds theta, the kT-th largest minimum it holds
+                // (found bit by bit, so at most kT - 1 lie above it); the
+                // points of every other chunk it holds have running minima of
+                // at most max(theta, the next-chunk bounds), since a chunk's
+                // second minimum never exceeds its best
                 uint64_t k[kK];
+                uint32_t mk[kK];
+                uint64_t kb = 0;
 #pragma unroll
-                for (int c = 0; c < kK; ++c)
-                    k[c] = (w < W && valid[c]) ? ((uint64_t)__float_as_uint(cm[c]) << 32) | (uint64_t)(0xffffffffu - cid[c]) : 0;
-                uint64_t th = 0;
-                for (int bit = 63; bit >= 0; --bit) {
-                    const uint64_t t = th | (1ull << bit);
+                for (int c = 0; c < kK; ++c) {
+                    const bool vc = w < W && valid[c];
+                    mk[c] = vc ? __float_as_uint(cm[c]) : 0u;
+                    k[c] = vc ? ((uint64_t)mk[c] << 32) | (uint64_t)(0xffffffffu - cid[c]) : 0;
+                    kb = k[c] > kb ? k[c] : kb;
+                }
+                uint32_t hbest;
+                const int ksrc = wave_argmax_key((uint32_t)(kb >> 32), 0xffffffffu - (uint32_t)kb, hbest);
+                const uint64_t ktop = ((uint64_t)hbest << 32) | rd_lane((uint32_t)kb, ksrc);
+                uint32_t th = 0;
+                for (int bit = 30; bit >= 0; --bit) {  // minima are non-negative floats
+                    const uint32_t t = th | (1u << bit);
                     int cnt = 0;
 #pragma unroll
-                    for (int c = 0; c < kK; ++c) cnt += __popcll(__ballot(k[c] >= t));
-                    if (cnt > kT) th = t;
+                    for (int c = 0; c < kK; ++c) cnt += __popcll(__ballot(mk[c] >= t));
+                    if (cnt >= kT) th = t;
                 }
                 const uint64_t below = (1ull << lane) - 1ull;
                 int base = 0;
 #pragma unroll
                 for (int c = 0; c < kK; ++c) {
-                    const bool in = k[c] > th;
+                    const bool in = k[c] != 0 && (mk[c] > th || k[c] == ktop);
                     const uint64_t m = __ballot(in);
                     if (in) {
                         Cand &o = s_cand[wid * kT + base + __popcll(m & below)];
@@ -943,7 +953,7 @@ __global__ __launch_bounds__(256) void k_fps_coop(
                 }
                 if (lane >= base && lane < kT) s_cand[wid * kT + lane].key = 0;
                 const float bmax = wave_max_f32_dpp(w < W ? bw : 0.f);
-                if (lane == 0) s_bnd[wid] = fmaxf(bmax, __uint_as_float((uint32_t)(th >> 32)));
+                if (lane == 0) s_bnd[wid] = fmaxf(bmax, __uint_as_float(th));
             }
             __syncthreads();
             const bool all_in = s_wok[0] && s_wok[1] && s_wok[2] && s_wok[3];
@@ -989,8 +999,7 @@ __global__ __launch_bounds__(256) void k_fps_coop(
                     uint32_t mmax;
                     const int src = wave_argmax_key(mb, ib, mmax);
                     const uint64_t best = ((uint64_t)mmax << 32) | (0xffffffffu - rd_lane(ib, src));
-                    const float gh = fmaxf(b0, wave_max_f32_dpp(hb));
-                    if (p > 0 && !(best > key_bound(gh))) break;
+                    if (p > 0 && (!(best > key_bound(b0)) || __ballot(!(best > key_bound(hb))))) break;
                     const float px = __uint_as_float(rd_lane(__float_as_uint(bx), src));
                     const float py = __uint_as_float(rd_lane(__float_as_uint(by), src));
                     const float pz = __uint_as_float(rd_lane(__float_as_uint(bz), src));
