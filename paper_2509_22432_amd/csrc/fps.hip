@@ -6,15 +6,15 @@
 // (minimum bits << 32 | ~point index), so ties go to the lowest index.
 //
 // * Large clouds: one cooperative launch per cloud.  The points are sorted
-//   in Morton order and cut into chunks of 64*m; chunk c belongs to
-//   workgroup c mod W, which keeps the chunk's bounding box, max key and
-//   argmax point in LDS.  A round updates only the chunks whose box lies
-//   closer to the new landmark than the chunk's max minimum (a point
-//   farther away cannot change), re-reduces the workgroup's max, publishes
-//   it to a two-slot ring in global memory and polls the W slots of the
-//   round: the ring replaces a grid barrier and a second reduction.  Only
-//   the 64-bit keys cross workgroups (the winner's coordinates are read
-//   from X), so no release/acquire fence and no L2 write-back is needed.
+//   in Morton order and cut into chunks; chunk c belongs to workgroup
+//   c mod W, which keeps the chunk's bounding box, best key and point and
+//   second minimum in LDS.  Landmarks are decided in exchanges of several
+//   at a time: the workgroups publish their best chunks, workgroup 0
+//   replays the greedy rule on them for as long as every unseen point is
+//   provably below the next pick, and the picks go back to all workgroups
+//   (the section "cooperative rounds" below gives the details).  Exchanged
+//   words carry the exchange number, so no release/acquire fence and no
+//   L2 write-back is needed.
 // * Small clouds (batches): one persistent workgroup per cloud over a
 //   row-major grid.  State per row of cells and per z-slab of rows; a
 //   round updates the points in the cells within the covering radius R of
@@ -479,13 +479,16 @@ __global__ __launch_bounds__(kPT) void k_fps_persist(
 // second-largest running minimum.  The landmarks are decided in exchanges
 // of up to kJ at a time:
 //  1. every workgroup applies the landmarks of the previous exchange to
-//     the chunks they can lower (box closer than the chunk's best minimum)
+//     the chunks they can lower (box closer than the chunk's best minimum;
+//     tested first against the union box of kG consecutive slots)
 //     and publishes its kK best chunks (best point, its coordinates, the
 //     chunk's second minimum and box) and the key of its next chunk;
-//  2. workgroup 0 collects the W records and replays the greedy rule on
-//     them: the next landmark is the best published candidate after the
-//     landmarks picked so far, accepted only while its key exceeds every
-//     bound on the unpublished points -- the next chunk's key, and per
+//  2. workgroup 0 collects the W records; each of its waves keeps its best
+//     key and the candidates above its kT-th largest minimum (which bounds
+//     the rest), and one wave replays the greedy rule on the kept ones:
+//     the next landmark is the best candidate after the landmarks picked
+//     so far, accepted only while its key exceeds every bound on the points
+//     not in view -- the next chunks' keys, the thresholds, and per
 //     published chunk min(second minimum, farthest box corner from each
 //     pick); the first pick is always exact (it is the global maximum);
 //  3. it publishes the picks and every workgroup reads them.
