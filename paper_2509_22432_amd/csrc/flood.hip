@@ -762,7 +762,7 @@ hipError_t flood_run(const flood_problem *pb, const flood_tuning &tu, const floo
     flood_workspace(pb, tu.cells_per_point, &sz);
     Carve c(ws, ws_bytes);
     GridWork g;
-    grid_carve(c, pb->B, pb->x_off, sz.total_cells, g);
+    grid_carve(c, pb->B, pb->x_off, tu.cells_per_point, g);
     int64_t nmax = 0;
     for (int d = 0; d < 4; ++d) nmax = sz.n[d] > nmax ? sz.n[d] : nmax;
     int64_t smax = 0;

@@ -1166,7 +1166,7 @@ hipError_t fps_run(const float *X, int32_t B, const int64_t *x_off, const int64_
     const int64_t np = x_off[B];
     Carve c(ws, ws_bytes);
     FpsWork w;
-    grid_carve(c, B, x_off, tc, w.grid);
+    grid_carve(c, B, x_off, fps_alpha(), w.grid);
     w.mind = c.take<float>(np);
     w.rkey = c.take<uint64_t>(tc + 1);
     w.state = c.take<FpsState>(B);

@@ -1,5 +1,6 @@
 // Uniform-grid binning of the point clouds by a device counting sort:
-// bounding box, grid parameters, per-cell histogram, exclusive scan, scatter.
+// bounding box, grid parameters, then a partition of the points into
+// buckets of consecutive cells and a per-bucket sort by cell in LDS.
 // The grid is the spatial index the flooding and landmark kernels scan; it
 // replaces the paper's presorted axis slices and Boolean masks (Sec. 4.2 and
 // its appendix) with cell lists that are contiguous in memory.
@@ -149,35 +150,84 @@ static int bbox_blocks(int32_t B, const int64_t *x_off) {
     return (int)(bx < 1 ? 1 : (bx > 1024 ? 1024 : bx));
 }
 
+// partition shape: blocks per cloud and cells per bucket (a cloud's bucket
+// counters and a bucket's cell counters both live in LDS)
+static constexpr int kPartTile = 8192;      // points per partition block, about
+static constexpr int kSortBlock = 1024;     // threads of a bucket-sort block
+static constexpr int kPU = 4;               // points a thread handles at once
+static constexpr int kMaxBuckets = 16384;   // buckets per cloud
+static constexpr int kMinShift = 10, kMaxShift = 15;
+struct PartShape {
+    int32_t bx, shift;
+    int64_t nbtot, nbmax;
+    bool ok;
+};
+static PartShape part_shape(int32_t B, const int64_t *x_off, float alpha) {
+    PartShape ps;
+    int64_t nmax = 0, capmax = 0;
+    for (int32_t b = 0; b < B; ++b) {
+        const int64_t n = x_off[b + 1] - x_off[b];
+        nmax = n > nmax ? n : nmax;
+        const int64_t cap = cells_cap(n, alpha);
+        capmax = cap > capmax ? cap : capmax;
+    }
+    int shift = kMinShift;
+    while (shift < kMaxShift && ((capmax + (1ll << shift) - 1) >> shift) > kMaxBuckets) ++shift;
+    ps.shift = shift;
+    ps.ok = ((capmax + (1ll << shift) - 1) >> shift) <= kMaxBuckets;
+    int64_t bx = (nmax + kPartTile - 1) / kPartTile;
+    ps.bx = (int32_t)(bx < 1 ? 1 : (bx > 1024 ? 1024 : bx));
+    ps.nbtot = 0;
+    ps.nbmax = 0;
+    for (int32_t b = 0; b < B; ++b) {
+        const int64_t nb = (cells_cap(x_off[b + 1] - x_off[b], alpha) + (1ll << shift) - 1) >> shift;
+        ps.nbtot += nb;
+        ps.nbmax = nb > ps.nbmax ? nb : ps.nbmax;
+    }
+    return ps;
+}
+
 size_t grid_workspace(int32_t B, const int64_t *x_off, float alpha, int64_t *total_cells) {
     int64_t tc = 0;
     for (int32_t b = 0; b < B; ++b) tc += cells_cap(x_off[b + 1] - x_off[b], alpha);
     if (total_cells) *total_cells = tc;
+    const PartShape ps = part_shape(B, x_off, alpha);
     int64_t np = x_off[B];
     size_t bytes = 0;
     bytes += sizeof(GridParam) * B + 256;
     bytes += sizeof(uint32_t) * 6 * B + 256;
     bytes += sizeof(float) * 6 * (size_t)B * bbox_blocks(B, x_off) + 256;
-    bytes += sizeof(float4) * np + 256;
-    bytes += sizeof(uint32_t) * np + 256;
-    bytes += sizeof(uint32_t) * (tc + 1) + 256;
-    bytes += sizeof(uint32_t) * tc + 256;
-    bytes += sizeof(uint32_t) * scan_tmp_elems(tc + 1) + 256;
+    bytes += sizeof(float4) * np + 256;                        // xs
+    bytes += sizeof(uint32_t) * (tc + 1) + 256;                // cell_start
+    bytes += sizeof(float4) * np + 256;                        // tmp_pt
+    bytes += sizeof(uint32_t) * (ps.nbtot + 1) + 256;          // bucket counts, then starts
+    bytes += sizeof(uint32_t) * ps.nbtot + 256;                // bucket cursors
+    bytes += sizeof(uint32_t) * scan_tmp_elems(ps.nbtot + 1) + 256;
+    bytes += sizeof(int64_t) * (B + 1) + 256;                  // bk_off
     return bytes;
 }
 
-void grid_carve(Carve &c, int32_t B, const int64_t *x_off, int64_t total_cells, GridWork &g) {
+void grid_carve(Carve &c, int32_t B, const int64_t *x_off, float alpha, GridWork &g) {
     const int64_t total_pts = x_off[B];
+    int64_t tc = 0;
+    for (int32_t b = 0; b < B; ++b) tc += cells_cap(x_off[b + 1] - x_off[b], alpha);
+    const PartShape ps = part_shape(B, x_off, alpha);
     g.gp = c.take<GridParam>(B);
     g.bbox = c.take<uint32_t>(6 * (size_t)B);
     g.bbox_blocks = bbox_blocks(B, x_off);
     g.bbox_part = c.take<float>(6 * (size_t)B * g.bbox_blocks);
     g.xs = c.take<float4>(total_pts);
-    g.pcell = c.take<uint32_t>(total_pts);
-    g.cell_start = c.take<uint32_t>(total_cells + 1);
-    g.cursor = c.take<uint32_t>(total_cells);
-    g.scan_tmp = c.take<uint32_t>(scan_tmp_elems(total_cells + 1));
-    g.total_cells = total_cells;
+    g.cell_start = c.take<uint32_t>(tc + 1);
+    g.tmp_pt = c.take<float4>(total_pts);
+    g.bstart = c.take<uint32_t>(ps.nbtot + 1);
+    g.bcursor = c.take<uint32_t>(ps.nbtot);
+    g.scan_tmp = c.take<uint32_t>(scan_tmp_elems(ps.nbtot + 1));
+    g.bk_off = c.take<int64_t>(B + 1);
+    g.bx = ps.ok ? ps.bx : 0;  // 0: a cloud needs more cells than the partition supports
+    g.shift = ps.shift;
+    g.nbtot = ps.nbtot;
+    g.nbmax = ps.nbmax;
+    g.total_cells = tc;
     g.total_pts = total_pts;
 }
 
@@ -268,9 +318,10 @@ __global__ __launch_bounds__(kBlock) void k_bbox_final(const float *part, int nb
 
 // one thread: grid parameters of every cloud (sequential prefix of the cell bases)
 __global__ void k_grid_params(const uint32_t *bbox, const int64_t *x_off, int32_t B, float alpha, int32_t max_dim,
-                              int64_t morton_lo, int64_t morton_hi, GridParam *gp) {
+                              int64_t morton_lo, int64_t morton_hi, int32_t shift, GridParam *gp, int64_t *bk_off) {
     if (blockIdx.x != 0 || threadIdx.x != 0) return;
     int64_t base = 0;
+    bk_off[0] = 0;
     for (int32_t b = 0; b < B; ++b) {
         GridParam g;
         int64_t n = x_off[b + 1] - x_off[b];
@@ -319,58 +370,203 @@ __global__ void k_grid_params(const uint32_t *bbox, const int64_t *x_off, int32_
         g.cells_cap = cap;
         gp[b] = g;
         base += cap;
+        bk_off[b + 1] = bk_off[b] + ((cap + (1ll << shift) - 1) >> shift);
     }
 }
 
 
-__global__ __launch_bounds__(kBlock) void k_count(const float *X, const GridParam *gp, uint32_t *pcell, uint32_t *counts) {
-    const int b = blockIdx.y;
-    const GridParam g = gp[b];
-    const int64_t lo = g.pt_base, hi = g.pt_base + g.npts;
-    for (int64_t i = lo + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < hi; i += (int64_t)gridDim.x * blockDim.x) {
-        int cx = bin_coord(X[3 * i], g.ox, g.inv_h, g.nx);
-        int cy = bin_coord(X[3 * i + 1], g.oy, g.inv_h, g.ny);
-        int cz = bin_coord(X[3 * i + 2], g.oz, g.inv_h, g.nz);
-        const uint32_t c = g.morton ? (uint32_t)g.cell_base + (spread3(cx) | (spread3(cy) << 1) | (spread3(cz) << 2))
-                                    : (uint32_t)(g.cell_base + ((int64_t)cz * g.ny + cy) * g.nx + cx);
-        pcell[i] = c;
-        atomicAdd(&counts[c], 1u);
+// global cell of a point (the binning rule of the grid)
+__device__ __forceinline__ uint32_t point_cell(float x, float y, float z, const GridParam &g) {
+    const int cx = bin_coord(x, g.ox, g.inv_h, g.nx);
+    const int cy = bin_coord(y, g.oy, g.inv_h, g.ny);
+    const int cz = bin_coord(z, g.oz, g.inv_h, g.nz);
+    return g.morton ? (uint32_t)g.cell_base + (spread3(cx) | (spread3(cy) << 1) | (spread3(cz) << 2))
+                    : (uint32_t)(g.cell_base + ((int64_t)cz * g.ny + cy) * g.nx + cx);
+}
+
+// points [lo, hi) of cloud b handled by partition block x
+__device__ __forceinline__ void part_range(const GridParam &g, int x, int bx, int64_t &lo, int64_t &hi) {
+    const int64_t tile = (g.npts + bx - 1) / bx;
+    lo = g.pt_base + (int64_t)x * tile;
+    hi = g.pt_base + g.npts;
+    if (lo + tile < hi) hi = lo + tile;
+}
+
+// counts of this block's points per bucket of its cloud, in LDS
+__device__ __forceinline__ void part_local_count(const float *X, const GridParam &g, int64_t lo, int64_t hi,
+                                                 int32_t shift, uint32_t *s_h) {
+    for (int64_t i0 = lo + threadIdx.x; i0 < hi; i0 += kBlock * kPU) {
+        uint32_t j[kPU];
+#pragma unroll
+        for (int u = 0; u < kPU; ++u) {
+            const int64_t i = i0 + (int64_t)u * kBlock;
+            j[u] = i < hi ? (point_cell(X[3 * i], X[3 * i + 1], X[3 * i + 2], g) - (uint32_t)g.cell_base) >> shift : 0u;
+        }
+#pragma unroll
+        for (int u = 0; u < kPU; ++u)
+            if (i0 + (int64_t)u * kBlock < hi) atomicAdd(&s_h[j[u]], 1u);
     }
 }
 
-__global__ void k_copy_u32(const uint32_t *src, uint32_t *dst, int64_t n) {
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-        dst[i] = src[i];
+// gridDim = (bx, B): bucket sizes (block counts added per nonzero bucket)
+__global__ __launch_bounds__(kBlock) void k_part_count(const float *X, const GridParam *gp, const int64_t *bk_off,
+                                                        int32_t shift, uint32_t *bcount) {
+    extern __shared__ uint32_t s_h[];
+    const int b = blockIdx.y, x = blockIdx.x, bx = gridDim.x;
+    const GridParam g = gp[b];
+    const int64_t g0 = bk_off[b], nb = bk_off[b + 1] - g0;
+    for (int64_t j = threadIdx.x; j < nb; j += kBlock) s_h[j] = 0u;
+    __syncthreads();
+    int64_t lo, hi;
+    part_range(g, x, bx, lo, hi);
+    part_local_count(X, g, lo, hi, shift, s_h);
+    __syncthreads();
+    for (int64_t j = threadIdx.x; j < nb; j += kBlock)
+        if (s_h[j]) atomicAdd(&bcount[g0 + j], s_h[j]);
 }
 
-__global__ __launch_bounds__(kBlock) void k_scatter(const float *X, const GridParam *gp, const uint32_t *pcell,
-                                                     uint32_t *cursor, float4 *xs) {
-    const int b = blockIdx.y;
+// gridDim = (bx, B): the block claims a run in each bucket it feeds (one
+// atomic per bucket) and moves its points there (positions from LDS)
+__global__ __launch_bounds__(kBlock) void k_part_scatter(const float *X, const GridParam *gp, const int64_t *bk_off,
+                                                          int32_t shift, uint32_t *bcursor, float4 *tmp_pt) {
+    extern __shared__ uint32_t s_h[];
+    const int b = blockIdx.y, x = blockIdx.x, bx = gridDim.x;
     const GridParam g = gp[b];
-    const int64_t lo = g.pt_base, hi = g.pt_base + g.npts;
-    for (int64_t i = lo + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < hi; i += (int64_t)gridDim.x * blockDim.x) {
-        uint32_t pos = atomicAdd(&cursor[pcell[i]], 1u);
-        xs[pos] = make_float4(X[3 * i], X[3 * i + 1], X[3 * i + 2], __int_as_float((int)i));
+    const int64_t g0 = bk_off[b], nb = bk_off[b + 1] - g0;
+    for (int64_t j = threadIdx.x; j < nb; j += kBlock) s_h[j] = 0u;
+    __syncthreads();
+    int64_t lo, hi;
+    part_range(g, x, bx, lo, hi);
+    part_local_count(X, g, lo, hi, shift, s_h);
+    __syncthreads();
+    for (int64_t j = threadIdx.x; j < nb; j += kBlock)
+        if (s_h[j]) s_h[j] = atomicAdd(&bcursor[g0 + j], s_h[j]);
+    __syncthreads();
+    for (int64_t i0 = lo + threadIdx.x; i0 < hi; i0 += kBlock * kPU) {
+        float4 v[kPU];
+        uint32_t pos[kPU];
+#pragma unroll
+        for (int u = 0; u < kPU; ++u) {
+            const int64_t i = i0 + (int64_t)u * kBlock;
+            if (i < hi) v[u] = make_float4(X[3 * i], X[3 * i + 1], X[3 * i + 2], __int_as_float((int)i));
+        }
+#pragma unroll
+        for (int u = 0; u < kPU; ++u)
+            if (i0 + (int64_t)u * kBlock < hi)
+                pos[u] = atomicAdd(&s_h[(point_cell(v[u].x, v[u].y, v[u].z, g) - (uint32_t)g.cell_base) >> shift], 1u);
+#pragma unroll
+        for (int u = 0; u < kPU; ++u)
+            if (i0 + (int64_t)u * kBlock < hi) tmp_pt[pos[u]] = v[u];
+    }
+}
+
+// exclusive scan of n <= NT * per values in LDS, in place (per: values per thread)
+template <int NT>
+__device__ void lds_exclusive_scan(uint32_t *v, int n, int per) {
+    __shared__ uint32_t s_w[NT / 64];
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const int a = tid * per, e = min(a + per, n);
+    uint32_t sum = 0;
+    for (int k = a; k < e; ++k) sum += v[k];
+    uint32_t incl = sum;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t y = __shfl_up(incl, o, 64);
+        if (lane >= o) incl += y;
+    }
+    if (lane == 63) s_w[wid] = incl;
+    __syncthreads();
+    uint32_t off = incl - sum;
+    for (int w = 0; w < wid; ++w) off += s_w[w];
+    for (int k = a; k < e; ++k) {
+        const uint32_t t = v[k];
+        v[k] = off;
+        off += t;
+    }
+    __syncthreads();
+}
+
+// one block per bucket: its points sorted by cell, its cells' starts
+__global__ __launch_bounds__(kSortBlock) void k_bucket_sort(const GridParam *gp, const int64_t *bk_off, int32_t B,
+                                                             int32_t shift, const uint32_t *bstart,
+                                                             const float4 *tmp_pt, uint32_t *cell_start, float4 *xs,
+                                                             int64_t nbtot, int64_t total_cells, int64_t total_pts) {
+    extern __shared__ uint32_t s_c[];
+    const int64_t gb = blockIdx.x;
+    int lo = 0, hi = B;  // cloud: the last b with bk_off[b] <= gb
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (bk_off[mid] <= gb) lo = mid;
+        else hi = mid;
+    }
+    const GridParam g = gp[lo];
+    const int64_t c0 = g.cell_base + ((gb - bk_off[lo]) << shift);
+    const int64_t cend = g.cell_base + g.cells_cap;
+    const int ncell = (int)((c0 + (1ll << shift) < cend ? c0 + (1ll << shift) : cend) - c0);
+    const uint32_t p0 = bstart[gb], p1 = bstart[gb + 1];
+    for (int k = threadIdx.x; k < ncell; k += kSortBlock) s_c[k] = 0u;
+    __syncthreads();
+    for (uint32_t q = p0 + threadIdx.x; q < p1; q += kSortBlock * kPU) {
+        uint32_t c[kPU];
+#pragma unroll
+        for (int u = 0; u < kPU; ++u) {
+            const uint32_t p = q + u * kSortBlock;
+            if (p < p1) {
+                const float4 v = tmp_pt[p];
+                c[u] = point_cell(v.x, v.y, v.z, g) - (uint32_t)c0;
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < kPU; ++u)
+            if (q + u * kSortBlock < p1) atomicAdd(&s_c[c[u]], 1u);
+    }
+    __syncthreads();
+    lds_exclusive_scan<kSortBlock>(s_c, ncell, (ncell + kSortBlock - 1) / kSortBlock);
+    for (int k = threadIdx.x; k < ncell; k += kSortBlock) cell_start[c0 + k] = p0 + s_c[k];
+    if (gb == nbtot - 1 && threadIdx.x == 0) cell_start[total_cells] = (uint32_t)total_pts;
+    __syncthreads();
+    for (uint32_t q = p0 + threadIdx.x; q < p1; q += kSortBlock * kPU) {
+        float4 v[kPU];
+        uint32_t c[kPU];
+#pragma unroll
+        for (int u = 0; u < kPU; ++u) {
+            const uint32_t p = q + u * kSortBlock;
+            if (p < p1) {
+                v[u] = tmp_pt[p];
+                c[u] = point_cell(v[u].x, v[u].y, v[u].z, g) - (uint32_t)c0;
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < kPU; ++u)
+            if (q + u * kSortBlock < p1) xs[p0 + atomicAdd(&s_c[c[u]], 1u)] = v[u];
     }
 }
 
 hipError_t grid_build(const float *X, int32_t B, const int64_t *x_off, const int64_t *x_off_d,
                       float alpha, GridWork &g, hipStream_t s, int32_t max_dim, int64_t morton_lo, int64_t morton_hi) {
-    int64_t nmax = 0;
-    for (int32_t b = 0; b < B; ++b) nmax = nmax > x_off[b + 1] - x_off[b] ? nmax : x_off[b + 1] - x_off[b];
-    int bx = (int)((nmax + kBlock * 8 - 1) / (kBlock * 8));
-    if (bx < 1) bx = 1;
-    if (bx > 4096) bx = 4096;
+    (void)x_off;
+    if (g.bx < 1) return hipErrorInvalidValue;  // a cloud with more cells than the partition supports
     hipLaunchKernelGGL(k_bbox, dim3(g.bbox_blocks, B), dim3(kBlock), 0, s, X, x_off_d, g.bbox_part);
     hipLaunchKernelGGL(k_bbox_final, dim3(B), dim3(kBlock), 0, s, g.bbox_part, g.bbox_blocks, g.bbox);
-    hipLaunchKernelGGL(k_grid_params, dim3(1), dim3(1), 0, s, g.bbox, x_off_d, B, alpha, max_dim, morton_lo, morton_hi, g.gp);
-    hipError_t e = fill_u32(g.cell_start, 0u, g.total_cells + 1, s);
+    hipLaunchKernelGGL(k_grid_params, dim3(1), dim3(1), 0, s, g.bbox, x_off_d, B, alpha, max_dim, morton_lo, morton_hi,
+                       g.shift, g.gp, g.bk_off);
+    hipError_t e = fill_u32(g.bstart, 0u, g.nbtot + 1, s);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_count, dim3(bx, B), dim3(kBlock), 0, s, X, g.gp, g.pcell, g.cell_start);
-    e = exclusive_scan_u32(g.cell_start, g.total_cells + 1, g.scan_tmp, s);
+    const size_t sh_part = sizeof(uint32_t) * (size_t)g.nbmax;
+    hipLaunchKernelGGL(k_part_count, dim3(g.bx, B), dim3(kBlock), sh_part, s, X, g.gp, g.bk_off, g.shift, g.bstart);
+    e = exclusive_scan_u32(g.bstart, g.nbtot + 1, g.scan_tmp, s);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_copy_u32, dim3(grid_blocks(g.total_cells)), dim3(kBlock), 0, s, g.cell_start, g.cursor, g.total_cells);
-    hipLaunchKernelGGL(k_scatter, dim3(bx, B), dim3(kBlock), 0, s, X, g.gp, g.pcell, g.cursor, g.xs);
+    e = copy_u32(g.bstart, g.bcursor, g.nbtot, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_part_scatter, dim3(g.bx, B), dim3(kBlock), sh_part, s, X, g.gp, g.bk_off, g.shift, g.bcursor,
+                       g.tmp_pt);
+    const size_t sh_bucket = sizeof(uint32_t) << g.shift;
+    if (sh_bucket > 65536) {
+        e = hipFuncSetAttribute((const void *)k_bucket_sort, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh_bucket);
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(k_bucket_sort, dim3((unsigned)g.nbtot), dim3(kSortBlock), sh_bucket, s, g.gp, g.bk_off, B,
+                       g.shift, g.bstart, g.tmp_pt, g.cell_start, g.xs, g.nbtot, g.total_cells, g.total_pts);
     return hipGetLastError();
 }
 

@@ -66,29 +66,40 @@ __device__ __forceinline__ uint32_t spread3(uint32_t v) {
     return v;
 }
 
-// cell coordinate of a coordinate value (the binning rule; NaN maps to 0)
+// cell coordinate of a coordinate value (the binning rule; NaN maps to 0,
+// +inf and values past the grid to n - 1)
 __device__ inline int bin_coord(float v, float o, float inv_h, int n) {
-    float t = (v - o) * inv_h;
-    int c = (t >= 0.f) ? (int)t : 0;
-    return c < n ? c : n - 1;
+    const float t = (v - o) * inv_h;
+    return (t >= 0.f) ? (t < (float)n ? (int)t : n - 1) : 0;
 }
 
 // ---- grid build (grid.hip) ----
+// The counting sort by cell runs in two partition passes with no atomics on
+// cells: cells are grouped per cloud in buckets of 2^shift consecutive
+// cells; bx blocks per cloud count and move their share of the points per
+// bucket (one device atomic per block and bucket it feeds), then one block
+// per bucket sorts its points by cell in LDS.
 struct GridWork {
     GridParam *gp;        // [B]
     uint32_t *bbox;       // [B][6] ordered keys: min xyz, max xyz
     float *bbox_part;     // [B][bbox_blocks][6] partial boxes
     int bbox_blocks;
-    float4 *xs;           // [sum N] (x, y, z, bits of global point row)
-    uint32_t *pcell;      // [sum N] global cell of each point (input order)
+    float4 *xs;           // [sum N] (x, y, z, bits of global point row), sorted by cell
     uint32_t *cell_start; // [total_cells + 1]
-    uint32_t *cursor;     // [total_cells]
-    uint32_t *scan_tmp;   // block sums for the scan
+    float4 *tmp_pt;       // [sum N] points grouped by bucket
+    uint32_t *bstart;     // [nbtot + 1] bucket sizes, then bucket starts
+    uint32_t *bcursor;    // [nbtot] bucket fill cursors
+    uint32_t *scan_tmp;   // block sums for the scan of bstart
+    int64_t *bk_off;      // [B + 1] first bucket of each cloud
+    int32_t bx;           // partition blocks per cloud
+    int32_t shift;        // log2 of the cells per bucket
+    int64_t nbtot;        // buckets over all clouds
+    int64_t nbmax;        // buckets of the largest cloud
     int64_t total_cells;
     int64_t total_pts;
 };
 size_t grid_workspace(int32_t B, const int64_t *x_off, float alpha, int64_t *total_cells);
-void grid_carve(Carve &c, int32_t B, const int64_t *x_off, int64_t total_cells, GridWork &g);
+void grid_carve(Carve &c, int32_t B, const int64_t *x_off, float alpha, GridWork &g);
 hipError_t grid_build(const float *X, int32_t B, const int64_t *x_off, const int64_t *x_off_d,
                       float alpha, GridWork &g, hipStream_t s, int32_t max_dim = 1 << 20,
                       int64_t morton_lo = INT64_MAX, int64_t morton_hi = INT64_MAX);
