@@ -30,6 +30,13 @@ namespace flood {
 static constexpr int kWaveBlock = 256;
 static constexpr int kU = 8;  // points per lane per step in the per-sample search
 
+// an open sample handed from phase A to phase B: its position and distance
+// bound, its id (simplex * interior samples + rank) and cloud
+struct __align__(16) OpenSample {
+    float4 p;  // x, y, z, squared-distance bound
+    uint32_t gid, cloud, pad0, pad1;
+};
+
 // ---------------------------------------------------------------------------
 // per-dimension helpers
 
@@ -157,7 +164,7 @@ __global__ __launch_bounds__(kWaveBlock) void k_flood_tiles(
     TileArgs a, const float *__restrict__ L, const int32_t *__restrict__ simp, const int64_t *__restrict__ s_off,
     const int64_t *__restrict__ tile_off, const float *__restrict__ seed, uint64_t *__restrict__ key,
     const GridParam *__restrict__ gp, const uint32_t *__restrict__ cs, const float4 *__restrict__ xs,
-    const uint32_t *__restrict__ order, uint64_t *__restrict__ hard, uint32_t *__restrict__ hard_count,
+    const uint32_t *__restrict__ order, OpenSample *__restrict__ hard, uint32_t *__restrict__ hard_count,
     unsigned long long *__restrict__ evals, unsigned long long *__restrict__ stats) {
     const int lane = threadIdx.x & 63;
     const int wpb = blockDim.x >> 6;
@@ -258,13 +265,10 @@ __global__ __launch_bounds__(kWaveBlock) void k_flood_tiles(
                     lz0 = fminf(lz0, sz[t]); lz1 = fmaxf(lz1, sz[t]);
                     bmax = fmaxf(bmax, best[t]);
                 }
-#pragma unroll
-            for (int o = 32; o > 0; o >>= 1) {
-                lx0 = fminf(lx0, __shfl_xor(lx0, o, 64)); lx1 = fmaxf(lx1, __shfl_xor(lx1, o, 64));
-                ly0 = fminf(ly0, __shfl_xor(ly0, o, 64)); ly1 = fmaxf(ly1, __shfl_xor(ly1, o, 64));
-                lz0 = fminf(lz0, __shfl_xor(lz0, o, 64)); lz1 = fmaxf(lz1, __shfl_xor(lz1, o, 64));
-                bmax = fmaxf(bmax, __shfl_xor(bmax, o, 64));
-            }
+            lx0 = wave_min_f32_dpp(lx0); lx1 = wave_max_f32_dpp(lx1);
+            ly0 = wave_min_f32_dpp(ly0); ly1 = wave_max_f32_dpp(ly1);
+            lz0 = wave_min_f32_dpp(lz0); lz1 = wave_max_f32_dpp(lz1);
+            bmax = wave_max_f32_dpp(bmax);
             // rows of box [lo,hi] minus box [olo,ohi], enumerated 64 at a time
             const int nyb = hi[1] - lo[1] + 1;
             const int nrows = nyb * (hi[2] - lo[2] + 1);
@@ -322,13 +326,8 @@ __global__ __launch_bounds__(kWaveBlock) void k_flood_tiles(
                     // the kept runs' points, flattened: 64 per coalesced load,
                     // staged in LDS and read back at one address by every lane
                     const uint32_t cnt = ((need_m >> lane) & 1ull) ? p1 - p0 : 0u;
-                    uint32_t incl = cnt;
-#pragma unroll
-                    for (int o = 1; o < 64; o <<= 1) {
-                        const uint32_t v = __shfl_up(incl, o, 64);
-                        if (lane >= o) incl += v;
-                    }
-                    const uint32_t total = __builtin_amdgcn_readlane(incl, 63);
+                    const uint32_t incl = wave_incl_sum(cnt);
+                    const uint32_t total = rd_lane(incl, 63);
                     sw_p0[lane] = p0;
                     sw_end[lane] = incl;
                     int nlive = 0;
@@ -420,8 +419,12 @@ __global__ __launch_bounds__(kWaveBlock) void k_flood_tiles(
         base = __shfl(base, 0, 64);
         if (push) {
             const uint32_t slot = base + (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
-            const uint32_t g_id = (uint32_t)(sj[t] * (int64_t)a.n_int + sq[t]);
-            hard[slot] = ((uint64_t)g_id << 32) | __float_as_uint(best[t]);
+            OpenSample o;
+            o.p = make_float4(sx[t], sy[t], sz[t], best[t]);
+            o.gid = (uint32_t)(sj[t] * (int64_t)a.n_int + sq[t]);
+            o.cloud = (uint32_t)b;
+            o.pad0 = o.pad1 = 0u;
+            hard[slot] = o;
         }
     }
     if (evals && lane == 0 && nev) atomicAdd(evals, nev);
@@ -506,13 +509,8 @@ __device__ bool ring_search(const GridParam &g, const uint32_t *__restrict__ cs,
             }
         }
         // flatten the 64 rows' points; each lane takes kU consecutive ones
-        uint32_t incl = cnt;
-#pragma unroll
-        for (int o = 1; o < 64; o <<= 1) {
-            const uint32_t v = __shfl_up(incl, o, 64);
-            if (lane >= o) incl += v;
-        }
-        const uint32_t total = __builtin_amdgcn_readlane(incl, 63);
+        const uint32_t incl = wave_incl_sum(cnt);
+        const uint32_t total = rd_lane(incl, 63);
         s_p0[lane] = p0;
         s_end[lane] = incl;
         __builtin_amdgcn_wave_barrier();
@@ -547,14 +545,10 @@ __device__ bool ring_search(const GridParam &g, const uint32_t *__restrict__ cs,
                     lex_min(lbd, lbi, dist2(sx, sy, sz, cc[u].x, cc[u].y, cc[u].z), __float_as_int(cc[u].w));
         }
         __builtin_amdgcn_wave_barrier();
-#pragma unroll
-        for (int o = 32; o > 0; o >>= 1) {
-            const float od = __shfl_xor(lbd, o, 64);
-            const int32_t oi = __shfl_xor(lbi, o, 64);
-            lex_min(lbd, lbi, od, oi);
-        }
-        bd = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(lbd)));
-        bi = __builtin_amdgcn_readfirstlane(lbi);
+        uint32_t mmin;  // distances are non-negative: float order is bit order
+        const int src = wave_argmin_pair(__float_as_uint(lbd), (uint32_t)lbi, mmin);
+        bd = __uint_as_float(mmin);
+        bi = (int32_t)rd_lane((uint32_t)lbi, src);
         if (retire) {
             if ((base & 511) == 448)
                 M = fmaxf(M, key_value(__hip_atomic_load(keyj, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)));
@@ -577,10 +571,15 @@ __device__ __forceinline__ int find_cloud(const int64_t *__restrict__ s_off, int
 static constexpr uint32_t kGrab = 4;    // queue entries a wave takes per atomic
 static constexpr uint32_t kSeg = 2048;  // queue segment of one XCD (spatially adjacent open samples)
 
+// queue position of the v-th entry an XCD takes (segments x, x+8, ... of
+// kSeg entries; increases with v)
+__device__ __forceinline__ uint32_t seg_index(uint32_t v, uint32_t xcd) {
+    return ((v / kSeg) * 8u + xcd) * kSeg + v % kSeg;
+}
+
 __global__ __launch_bounds__(kWaveBlock) void k_flood_deep(
-    DeepArgs a, const float *__restrict__ L, const int32_t *__restrict__ simp, const int64_t *__restrict__ s_off,
-    const float *__restrict__ seed, uint64_t *__restrict__ key, const GridParam *__restrict__ gp,
-    const uint32_t *__restrict__ cs, const float4 *__restrict__ xs, const uint64_t *__restrict__ queue,
+    DeepArgs a, const float *__restrict__ seed, uint64_t *__restrict__ key, const GridParam *__restrict__ gp,
+    const uint32_t *__restrict__ cs, const float4 *__restrict__ xs, const OpenSample *__restrict__ queue,
     const uint32_t *__restrict__ queue_count, uint32_t *__restrict__ queue_next,
     unsigned long long *__restrict__ evals, unsigned long long *__restrict__ stats) {
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
@@ -596,25 +595,35 @@ __global__ __launch_bounds__(kWaveBlock) void k_flood_deep(
         uint32_t v0 = 0;
         if (lane == 0) v0 = atomicAdd(&queue_next[xcd], kGrab);
         v0 = __builtin_amdgcn_readfirstlane(v0);
-        if (((v0 / kSeg) * 8u + xcd) * kSeg + v0 % kSeg >= n) break;
-        for (uint32_t vq = v0; vq < v0 + kGrab; ++vq) {
-            const uint32_t i = ((vq / kSeg) * 8u + xcd) * kSeg + vq % kSeg;  // increases with vq
-            if (i >= n) break;
-            const uint64_t e = queue[i];
-            const uint32_t gid = (uint32_t)(e >> 32);
-            float bd = __uint_as_float((uint32_t)e);
-            int32_t bi = 0x7fffffff;
+        if (seg_index(v0, xcd) >= n) break;
+        // lanes 0..kGrab-1 fetch the grabbed entries and their simplices'
+        // running values together (a stale value only retires less)
+        float4 qp = make_float4(0.f, 0.f, 0.f, 0.f);
+        uint32_t qg = 0, qc = 0;
+        float qm = 0.f;
+        if (lane < (int)kGrab) {
+            const uint32_t i = seg_index(v0 + lane, xcd);
+            if (i < n) {
+                const OpenSample o = queue[i];
+                qp = o.p;
+                qg = o.gid;
+                qc = o.cloud;
+                const uint32_t j = o.gid / (uint32_t)a.n_int;
+                qm = fmaxf(seed[j], key_value(__hip_atomic_load(&key[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)));
+            }
+        }
+        for (int u = 0; u < (int)kGrab; ++u) {
+            if (seg_index(v0 + u, xcd) >= n) break;
+            const float sx = __uint_as_float(__builtin_amdgcn_readlane(__float_as_uint(qp.x), u));
+            const float sy = __uint_as_float(__builtin_amdgcn_readlane(__float_as_uint(qp.y), u));
+            const float sz = __uint_as_float(__builtin_amdgcn_readlane(__float_as_uint(qp.z), u));
+            float bd = __uint_as_float(__builtin_amdgcn_readlane(__float_as_uint(qp.w), u));
+            float M = __uint_as_float(__builtin_amdgcn_readlane(__float_as_uint(qm), u));
+            const uint32_t gid = __builtin_amdgcn_readlane(qg, u);
+            const GridParam g = gp[__builtin_amdgcn_readlane(qc, u)];
             const int64_t j = gid / (uint32_t)a.n_int;
             const int q = (int)(gid % (uint32_t)a.n_int);
-            const GridParam g = gp[find_cloud(s_off, a.B, j)];
-            int comp[4];
-            if (a.d == 0) comp[0] = a.k;
-            else unrank_interior(q, a.d, a.k, comp);
-            int32_t v[4];
-            simplex_vertices(simp, a.d, j, v);
-            float sx, sy, sz;
-            sample_point(L, v, comp, a.d, a.k, sx, sy, sz);
-            float M = fmaxf(seed[j], key_value(__hip_atomic_load(&key[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)));
+            int32_t bi = 0x7fffffff;
             const bool retired = ring_search(g, cs, xs, sx, sy, sz, bd, bi, a.d > 0, M, &key[j], s_p0[wid],
                                              s_end[wid], lane, nev);
             if (!retired && lane == 0) publish(key, seed, (int32_t)j, q, bd, a.d == 0);
@@ -722,7 +731,7 @@ size_t flood_workspace(const flood_problem *pb, float alpha, FloodSizes *sz) {
     }
     bytes += sizeof(float) * (nmax + 1) + 256;        // seed
     bytes += sizeof(uint64_t) * (nmax + 1) + 256;     // key
-    bytes += sizeof(uint64_t) * (smax + 1) + 256;     // open-sample queue
+    bytes += sizeof(OpenSample) * (smax + 1) + 256;   // open-sample queue
     int64_t bkmax = 0;
     for (int d = 0; d < 4; ++d) {
         int64_t bk = 0;
@@ -748,7 +757,7 @@ size_t flood_workspace(const flood_problem *pb, float alpha, FloodSizes *sz) {
 template <int T>
 static void launch_tiles(const TileArgs &ta, int wpb, hipStream_t s, const float *L, const int32_t *simp,
                          const int64_t *s_off, const int64_t *tile_off, const float *seed, uint64_t *key,
-                         const GridWork &g, const uint32_t *order, uint64_t *hard, uint32_t *hard_count,
+                         const GridWork &g, const uint32_t *order, OpenSample *hard, uint32_t *hard_count,
                          uint64_t *evals, uint64_t *stats) {
     const int64_t nb = (ta.n_tiles + wpb - 1) / wpb;
     hipLaunchKernelGGL(k_flood_tiles<T>, dim3((unsigned)nb), dim3(64 * wpb), 0, s, ta, L, simp, s_off, tile_off,
@@ -772,7 +781,7 @@ hipError_t flood_run(const flood_problem *pb, const flood_tuning &tu, const floo
     }
     float *seed = c.take<float>(nmax + 1);
     uint64_t *key = c.take<uint64_t>(nmax + 1);
-    uint64_t *hard = c.take<uint64_t>(smax + 1);
+    OpenSample *hard = c.take<OpenSample>(smax + 1);
     uint32_t *counters = c.take<uint32_t>(16);  // [0] open samples, [8..15] per-XCD queue cursors
     int64_t bkmax = 0;
     for (int d = 0; d < 4; ++d) {
@@ -856,7 +865,7 @@ hipError_t flood_run(const flood_problem *pb, const flood_tuning &tu, const floo
                 da.k = pb->k;
                 da.n_int = (int32_t)nint;
                 da.B = pb->B;
-                hipLaunchKernelGGL(k_flood_deep, dim3(2048), dim3(256), 0, s, da, pb->Lxyz, simp, soff_d, seed, key,
+                hipLaunchKernelGGL(k_flood_deep, dim3(2048), dim3(256), 0, s, da, seed, key,
                                    g.gp, g.cell_start, g.xs, hard, counters, counters + 8,
                                    (unsigned long long *)out->evals, (unsigned long long *)out->stats);
                 if (out->tile_events[3 * d + 2]) {

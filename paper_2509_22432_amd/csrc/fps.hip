@@ -91,43 +91,6 @@ __device__ __forceinline__ uint64_t wave_max_u64(uint64_t v) {
     return v;
 }
 
-// DPP lane moves within rows of 16 lanes (quad_perm xor 1, xor 2, then the
-// half-row and row mirrors): after the four steps every lane of a row holds
-// the row's reduction; the four rows are combined through scalar reads
-template <int CTRL>
-__device__ __forceinline__ uint32_t dpp_mov(uint32_t v) {
-    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, 0xf, 0xf, true);
-}
-__device__ __forceinline__ uint32_t rd_lane(uint32_t v, int l) { return (uint32_t)__builtin_amdgcn_readlane((int)v, l); }
-
-template <int CTRL>
-__device__ __forceinline__ uint32_t dpp_max_u32(uint32_t v) { return max(v, dpp_mov<CTRL>(v)); }
-template <int CTRL>
-__device__ __forceinline__ uint32_t dpp_min_u32(uint32_t v) { return min(v, dpp_mov<CTRL>(v)); }
-
-// the lane holding the wave's largest key (mb << 32) | ~id: the largest mb,
-// and among equal mb the lowest id (all 64 lanes active); mmax gets that mb
-__device__ __forceinline__ int wave_argmax_key(uint32_t mb, uint32_t id, uint32_t &mmax) {
-    uint32_t v = dpp_max_u32<0x140>(dpp_max_u32<0x141>(dpp_max_u32<0x4e>(dpp_max_u32<0xb1>(mb))));
-    mmax = max(max(rd_lane(v, 0), rd_lane(v, 16)), max(rd_lane(v, 32), rd_lane(v, 48)));
-    const uint64_t tied = __ballot(mb == mmax);
-    if (__popcll(tied) == 1) return __ffsll((unsigned long long)tied) - 1;
-    uint32_t u = mb == mmax ? id : 0xffffffffu;
-    u = dpp_min_u32<0x140>(dpp_min_u32<0x141>(dpp_min_u32<0x4e>(dpp_min_u32<0xb1>(u))));
-    const uint32_t umin = min(min(rd_lane(u, 0), rd_lane(u, 16)), min(rd_lane(u, 32), rd_lane(u, 48)));
-    return __ffsll((unsigned long long)__ballot(mb == mmax && id == umin)) - 1;
-}
-
-__device__ __forceinline__ float wave_max_f32_dpp(float v) {
-    v = fmaxf(v, __uint_as_float(dpp_mov<0xb1>(__float_as_uint(v))));
-    v = fmaxf(v, __uint_as_float(dpp_mov<0x4e>(__float_as_uint(v))));
-    v = fmaxf(v, __uint_as_float(dpp_mov<0x141>(__float_as_uint(v))));
-    v = fmaxf(v, __uint_as_float(dpp_mov<0x140>(__float_as_uint(v))));
-    const float a = fmaxf(__uint_as_float(rd_lane(__float_as_uint(v), 0)), __uint_as_float(rd_lane(__float_as_uint(v), 16)));
-    const float b = fmaxf(__uint_as_float(rd_lane(__float_as_uint(v), 32)), __uint_as_float(rd_lane(__float_as_uint(v), 48)));
-    return fmaxf(a, b);
-}
-
 __device__ __forceinline__ void finish_round(int32_t t, int32_t nl, uint64_t k, int64_t o, int64_t pt_base,
                                              const float *__restrict__ X, int32_t *__restrict__ idx_out,
                                              float *__restrict__ radius, float &lx, float &ly, float &lz,
