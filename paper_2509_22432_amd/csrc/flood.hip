@@ -477,7 +477,8 @@ __device__ __forceinline__ void lex_min(float &bd, int32_t &bi, float od, int32_
 // initial bd, unless `retire` is set and the bound fell below M (then the
 // function returns true early and (bd, bi) is only an upper bound).
 // s_p0 / s_end: 64 entries of LDS per wave.
-__device__ bool ring_search(const GridParam &g, const uint32_t *__restrict__ cs, const float4 *__restrict__ xs,
+__device__ bool ring_search(const GridParam &g, const uint32_t *__restrict__ cs, const uint32_t *__restrict__ occ,
+                            const float4 *__restrict__ xs,
                             float sx, float sy, float sz, float &bd, int32_t &bi, bool retire, float &M,
                             const uint64_t *__restrict__ keyj, uint32_t *s_p0, uint32_t *s_end, int lane,
                             unsigned long long &nev) {
@@ -504,8 +505,10 @@ __device__ bool ring_search(const GridParam &g, const uint32_t *__restrict__ cs,
                 const int x0 = cell_of(sx - w, g.ox, g.inv_h, g.nx);
                 const int x1 = cell_of(sx + w, g.ox, g.inv_h, g.nx);
                 const int64_t c0 = g.cell_base + ((int64_t)z * g.ny + y) * g.nx;
-                p0 = cs[c0 + x0];
-                cnt = cs[c0 + x1 + 1] - p0;
+                if (any_occupied(occ, c0 + x0, c0 + x1)) {  // the offsets only for a run that holds points
+                    p0 = cs[c0 + x0];
+                    cnt = cs[c0 + x1 + 1] - p0;
+                }
             }
         }
         // flatten the 64 rows' points; each lane takes kU consecutive ones
@@ -579,7 +582,8 @@ __device__ __forceinline__ uint32_t seg_index(uint32_t v, uint32_t xcd) {
 
 __global__ __launch_bounds__(kWaveBlock) void k_flood_deep(
     DeepArgs a, const float *__restrict__ seed, uint64_t *__restrict__ key, const GridParam *__restrict__ gp,
-    const uint32_t *__restrict__ cs, const float4 *__restrict__ xs, const OpenSample *__restrict__ queue,
+    const uint32_t *__restrict__ cs, const uint32_t *__restrict__ occ, const float4 *__restrict__ xs,
+    const OpenSample *__restrict__ queue,
     const uint32_t *__restrict__ queue_count, uint32_t *__restrict__ queue_next,
     unsigned long long *__restrict__ evals, unsigned long long *__restrict__ stats) {
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
@@ -624,7 +628,7 @@ __global__ __launch_bounds__(kWaveBlock) void k_flood_deep(
             const int64_t j = gid / (uint32_t)a.n_int;
             const int q = (int)(gid % (uint32_t)a.n_int);
             int32_t bi = 0x7fffffff;
-            const bool retired = ring_search(g, cs, xs, sx, sy, sz, bd, bi, a.d > 0, M, &key[j], s_p0[wid],
+            const bool retired = ring_search(g, cs, occ, xs, sx, sy, sz, bd, bi, a.d > 0, M, &key[j], s_p0[wid],
                                              s_end[wid], lane, nev);
             if (!retired && lane == 0) publish(key, seed, (int32_t)j, q, bd, a.d == 0);
         }
@@ -640,7 +644,8 @@ __global__ __launch_bounds__(kWaveBlock) void k_flood_deep(
 __global__ __launch_bounds__(kWaveBlock) void k_winner_search(
     int d, int k, int64_t n, int32_t B, const float *__restrict__ L, const int32_t *__restrict__ simp,
     const int64_t *__restrict__ s_off, const uint64_t *__restrict__ key, const GridParam *__restrict__ gp,
-    const uint32_t *__restrict__ cs, const float4 *__restrict__ xs, int32_t *__restrict__ win_x) {
+    const uint32_t *__restrict__ cs, const uint32_t *__restrict__ occ, const float4 *__restrict__ xs,
+    int32_t *__restrict__ win_x) {
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     __shared__ uint32_t s_p0[kWaveBlock / 64][64], s_end[kWaveBlock / 64][64];
     const int64_t j = xcd_remap(blockIdx.x, gridDim.x) * (blockDim.x >> 6) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -662,7 +667,7 @@ __global__ __launch_bounds__(kWaveBlock) void k_winner_search(
     float M = 0.f;
     unsigned long long nev = 0;
     const GridParam g = gp[find_cloud(s_off, B, j)];
-    ring_search(g, cs, xs, sx, sy, sz, bd, bi, false, M, nullptr, s_p0[wid], s_end[wid], lane, nev);
+    ring_search(g, cs, occ, xs, sx, sy, sz, bd, bi, false, M, nullptr, s_p0[wid], s_end[wid], lane, nev);
     if (lane == 0) win_x[j] = bi;
 }
 
@@ -866,7 +871,7 @@ hipError_t flood_run(const flood_problem *pb, const flood_tuning &tu, const floo
                 da.n_int = (int32_t)nint;
                 da.B = pb->B;
                 hipLaunchKernelGGL(k_flood_deep, dim3(2048), dim3(256), 0, s, da, seed, key,
-                                   g.gp, g.cell_start, g.xs, hard, counters, counters + 8,
+                                   g.gp, g.cell_start, g.occ, g.xs, hard, counters, counters + 8,
                                    (unsigned long long *)out->evals, (unsigned long long *)out->stats);
                 if (out->tile_events[3 * d + 2]) {
                     e = hipEventRecord((hipEvent_t)out->tile_events[3 * d + 2], s);
@@ -879,7 +884,7 @@ hipError_t flood_run(const flood_problem *pb, const flood_tuning &tu, const floo
                            d > 0 ? out->win_x[d - 1] : nullptr, d > 0 ? out->win_a[d - 1] : nullptr, out->f[d],
                            out->win_x[d], out->win_a[d]);
         hipLaunchKernelGGL(k_winner_search, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, s, d, pb->k, n, pb->B,
-                           pb->Lxyz, simp, soff_d, key, g.gp, g.cell_start, g.xs, out->win_x[d]);
+                           pb->Lxyz, simp, soff_d, key, g.gp, g.cell_start, g.occ, g.xs, out->win_x[d]);
         e = hipGetLastError();
         if (e != hipSuccess) return e;
     }

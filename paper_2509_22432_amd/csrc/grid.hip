@@ -199,6 +199,7 @@ size_t grid_workspace(int32_t B, const int64_t *x_off, float alpha, int64_t *tot
     bytes += sizeof(float) * 6 * (size_t)B * bbox_blocks(B, x_off) + 256;
     bytes += sizeof(float4) * np + 256;                        // xs
     bytes += sizeof(uint32_t) * (tc + 1) + 256;                // cell_start
+    bytes += sizeof(uint32_t) * (tc / 32 + 2) + 256;           // occupancy bits
     bytes += sizeof(float4) * np + 256;                        // tmp_pt
     bytes += sizeof(uint32_t) * (ps.nbtot + 1) + 256;          // bucket counts, then starts
     bytes += sizeof(uint32_t) * ps.nbtot + 256;                // bucket cursors
@@ -218,6 +219,7 @@ void grid_carve(Carve &c, int32_t B, const int64_t *x_off, float alpha, GridWork
     g.bbox_part = c.take<float>(6 * (size_t)B * g.bbox_blocks);
     g.xs = c.take<float4>(total_pts);
     g.cell_start = c.take<uint32_t>(tc + 1);
+    g.occ = c.take<uint32_t>(tc / 32 + 2);
     g.tmp_pt = c.take<float4>(total_pts);
     g.bstart = c.take<uint32_t>(ps.nbtot + 1);
     g.bcursor = c.take<uint32_t>(ps.nbtot);
@@ -542,6 +544,21 @@ __global__ __launch_bounds__(kSortBlock) void k_bucket_sort(const GridParam *gp,
     }
 }
 
+// one thread per 32 cells: the occupancy bits
+__global__ __launch_bounds__(kBlock) void k_occ_bits(const uint32_t *cell_start, int64_t total_cells, uint32_t *occ) {
+    const int64_t w = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int64_t c0 = w * 32;
+    if (c0 >= total_cells) return;
+    uint32_t m = 0, prev = cell_start[c0];
+    const int n = (int)(total_cells - c0 < 32 ? total_cells - c0 : 32);
+    for (int i = 0; i < n; ++i) {
+        const uint32_t next = cell_start[c0 + i + 1];
+        m |= (next > prev ? 1u : 0u) << i;
+        prev = next;
+    }
+    occ[w] = m;
+}
+
 hipError_t grid_build(const float *X, int32_t B, const int64_t *x_off, const int64_t *x_off_d,
                       float alpha, GridWork &g, hipStream_t s, int32_t max_dim, int64_t morton_lo, int64_t morton_hi) {
     (void)x_off;
@@ -567,6 +584,9 @@ hipError_t grid_build(const float *X, int32_t B, const int64_t *x_off, const int
     }
     hipLaunchKernelGGL(k_bucket_sort, dim3((unsigned)g.nbtot), dim3(kSortBlock), sh_bucket, s, g.gp, g.bk_off, B,
                        g.shift, g.bstart, g.tmp_pt, g.cell_start, g.xs, g.nbtot, g.total_cells, g.total_pts);
+    const int64_t nw = (g.total_cells + 31) / 32;
+    hipLaunchKernelGGL(k_occ_bits, dim3((unsigned)((nw + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, g.cell_start,
+                       g.total_cells, g.occ);
     return hipGetLastError();
 }
 

@@ -73,6 +73,18 @@ __device__ inline int bin_coord(float v, float o, float inv_h, int n) {
     return (t >= 0.f) ? (t < (float)n ? (int)t : n - 1) : 0;
 }
 
+// any occupied cell among global cells [a, b] (a <= b), from the occupancy bits
+__device__ __forceinline__ bool any_occupied(const uint32_t *__restrict__ occ, int64_t a, int64_t b) {
+    const int64_t w0 = a >> 5, w1 = b >> 5;
+    for (int64_t w = w0; w <= w1; ++w) {
+        uint32_t m = occ[w];
+        if (w == w0) m &= 0xffffffffu << (a & 31);
+        if (w == w1) m &= 0xffffffffu >> (31 - (b & 31));
+        if (m) return true;
+    }
+    return false;
+}
+
 // ---- wave primitives (DPP) ----
 // DPP lane moves within rows of 16 lanes (quad_perm xor 1, xor 2, then the
 // half-row and row mirrors): after the four steps every lane of a row holds
@@ -163,6 +175,7 @@ struct GridWork {
     int bbox_blocks;
     float4 *xs;           // [sum N] (x, y, z, bits of global point row), sorted by cell
     uint32_t *cell_start; // [total_cells + 1]
+    uint32_t *occ;        // [total_cells / 32 + 1] bit c set: cell c holds points
     float4 *tmp_pt;       // [sum N] points grouped by bucket
     uint32_t *bstart;     // [nbtot + 1] bucket sizes, then bucket starts
     uint32_t *bcursor;    // [nbtot] bucket fill cursors
