@@ -28,7 +28,7 @@
 namespace flood {
 
 static constexpr int kWaveBlock = 256;
-static constexpr int kU = 8;  // points per lane per step in the per-sample search
+static constexpr int kU = 4;  // points per lane per step in the per-sample search
 
 // an open sample handed from phase A to phase B: its position and distance
 // bound, its id (simplex * interior samples + rank) and cloud
@@ -160,7 +160,7 @@ __device__ __forceinline__ void publish(uint64_t *key, const float *seed, int32_
 }
 
 template <int T>
-__global__ __launch_bounds__(kWaveBlock) void k_flood_tiles(
+__global__ __launch_bounds__(kWaveBlock) __attribute__((amdgpu_waves_per_eu(T == 1 ? 8 : 1, 8))) void k_flood_tiles(
     TileArgs a, const float *__restrict__ L, const int32_t *__restrict__ simp, const int64_t *__restrict__ s_off,
     const int64_t *__restrict__ tile_off, const float *__restrict__ seed, uint64_t *__restrict__ key,
     const GridParam *__restrict__ gp, const uint32_t *__restrict__ cs, const float4 *__restrict__ xs,
@@ -580,7 +580,7 @@ __device__ __forceinline__ uint32_t seg_index(uint32_t v, uint32_t xcd) {
     return ((v / kSeg) * 8u + xcd) * kSeg + v % kSeg;
 }
 
-__global__ __launch_bounds__(kWaveBlock) void k_flood_deep(
+__global__ __launch_bounds__(kWaveBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_flood_deep(
     DeepArgs a, const float *__restrict__ seed, uint64_t *__restrict__ key, const GridParam *__restrict__ gp,
     const uint32_t *__restrict__ cs, const uint32_t *__restrict__ occ, const float4 *__restrict__ xs,
     const OpenSample *__restrict__ queue,
