@@ -29,6 +29,7 @@ namespace flood {
 
 static constexpr int kWaveBlock = 256;
 static constexpr int kU = 4;  // points per lane per step in the per-sample search
+static constexpr int kStage = 128;  // points staged in LDS per pass of the tile search
 
 // an open sample handed from phase A to phase B: its position and distance
 // bound, its id (simplex * interior samples + rank) and cloud
@@ -168,7 +169,7 @@ __global__ __launch_bounds__(kWaveBlock) __attribute__((amdgpu_waves_per_eu(T ==
     unsigned long long *__restrict__ evals, unsigned long long *__restrict__ stats) {
     const int lane = threadIdx.x & 63;
     const int wpb = blockDim.x >> 6;
-    __shared__ float4 s_pt[kWaveBlock / 64][64];
+    __shared__ float4 s_pt[kWaveBlock / 64][kStage];
     __shared__ uint32_t s_p0[kWaveBlock / 64][64], s_end[kWaveBlock / 64][64];
     float4 *sw_pt = s_pt[threadIdx.x >> 6];
     uint32_t *sw_p0 = s_p0[threadIdx.x >> 6], *sw_end = s_end[threadIdx.x >> 6];
@@ -336,23 +337,37 @@ __global__ __launch_bounds__(kWaveBlock) __attribute__((amdgpu_waves_per_eu(T ==
                     nev += (unsigned long long)total * (unsigned long long)nlive;
                     __builtin_amdgcn_wave_barrier();
                     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-                    for (uint32_t b0 = 0; b0 < total; b0 += 64) {
-                        const uint32_t k = b0 + (uint32_t)lane;
-                        float4 c = make_float4(INFINITY, INFINITY, INFINITY, 0.f);
-                        if (k < total) {
-                            int rr = 0, hi_r = 63;  // first run whose inclusive end exceeds k
-                            while (rr < hi_r) {
-                                const int mid = (rr + hi_r) >> 1;
-                                if (sw_end[mid] > k) hi_r = mid;
-                                else rr = mid + 1;
+                    // kStage points per pass (kStage / 64 per lane); the next
+                    // pass's loads are issued before this pass is evaluated
+                    auto fetch = [&](uint32_t b0, float4 (&c)[kStage / 64]) {
+#pragma unroll
+                        for (int u = 0; u < kStage / 64; ++u) {
+                            const uint32_t k = b0 + (uint32_t)(u * 64 + lane);
+                            c[u] = make_float4(INFINITY, INFINITY, INFINITY, 0.f);
+                            if (k < total) {
+                                int rr = 0, hi_r = 63;  // first run whose inclusive end exceeds k
+                                while (rr < hi_r) {
+                                    const int mid = (rr + hi_r) >> 1;
+                                    if (sw_end[mid] > k) hi_r = mid;
+                                    else rr = mid + 1;
+                                }
+                                c[u] = xs[sw_p0[rr] + (k - (rr ? sw_end[rr - 1] : 0u))];
                             }
-                            c = xs[sw_p0[rr] + (k - (rr ? sw_end[rr - 1] : 0u))];
                         }
+                    };
+                    float4 cn[kStage / 64];
+                    fetch(0, cn);
+                    for (uint32_t b0 = 0; b0 < total; b0 += kStage) {
+                        float4 cc[kStage / 64];
+#pragma unroll
+                        for (int u = 0; u < kStage / 64; ++u) cc[u] = cn[u];
+                        if (b0 + kStage < total) fetch(b0 + kStage, cn);
                         __builtin_amdgcn_wave_barrier();
-                        sw_pt[lane] = c;
+#pragma unroll
+                        for (int u = 0; u < kStage / 64; ++u) sw_pt[u * 64 + lane] = cc[u];
                         __builtin_amdgcn_wave_barrier();
                         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-                        const int n4 = (int)((min(total - b0, 64u) + 3u) & ~3u);
+                        const int n4 = (int)((min(total - b0, (uint32_t)kStage) + 3u) & ~3u);
                         for (int j = 0; j < n4; j += 4) {
                             const float4 c0 = sw_pt[j], c1 = sw_pt[j + 1], c2 = sw_pt[j + 2], c3 = sw_pt[j + 3];
 #pragma unroll
