@@ -586,7 +586,7 @@ __device__ __forceinline__ int find_cloud(const int64_t *__restrict__ s_off, int
     return lo_b;
 }
 
-static constexpr uint32_t kGrab = 4;    // queue entries a wave takes per atomic
+static constexpr uint32_t kGrab = 2;    // queue entries a wave takes per atomic
 static constexpr uint32_t kSeg = 2048;  // queue segment of one XCD (spatially adjacent open samples)
 
 // queue position of the v-th entry an XCD takes (segments x, x+8, ... of
