@@ -22,6 +22,7 @@
 //   keys of the touched rows and slabs (slab keys live in LDS) and takes
 //   the argmax over the slabs.  Round 0 runs as three dense launches.
 #include <algorithm>
+#include <type_traits>
 
 #include "internal.hpp"
 
@@ -466,6 +467,7 @@ static constexpr int64_t kCoopMin = 1 << 19;      // clouds of at least this man
 static constexpr int kSpinLimit = 1 << 22;        // polls of one exchange before the launch gives up
 static constexpr int kK = 2;                      // candidates a workgroup publishes
 static constexpr int kJ = 32;                     // landmarks decided per exchange, at most
+using LMask = std::conditional_t<(kJ > 32), uint64_t, uint32_t>;  // a set of an exchange's landmarks
 static constexpr int kT = 16;                     // candidates each leader wave keeps for the replay
 
 struct CoopArgs {
@@ -530,6 +532,12 @@ __device__ __forceinline__ void top3_insert(uint64_t (&k)[3], int (&s)[3], uint6
     }
 }
 
+__device__ __forceinline__ uint32_t uniform_mask(uint32_t m) { return __builtin_amdgcn_readfirstlane(m); }
+__device__ __forceinline__ uint64_t uniform_mask(uint64_t m) {
+    return (uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)m) |
+           ((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(m >> 32)) << 32);
+}
+
 template <int LM>
 __global__ __launch_bounds__(256) void k_fps_coop(
     CoopArgs a, const float *__restrict__ X, const GridParam *__restrict__ gp, const float4 *__restrict__ xs,
@@ -544,7 +552,7 @@ __global__ __launch_bounds__(256) void k_fps_coop(
     static_assert(1 + 12 * kK <= kRec && 1 + 12 * kK <= 64 && 1 + 5 * kJ <= kDec && kDec <= 64 * DH && kK <= 2,
                   "exchange layout");
     static_assert(NW * kT % 64 == 0 && kT <= 64, "whole kept candidates per lane of the replaying wave");
-    static_assert(kJ <= 32, "landmark masks of 32 bits");
+    static_assert(kJ <= 8 * (int)sizeof(LMask), "landmark masks");
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ float s_pk[kJ][3];       // landmarks to apply
     __shared__ int s_np, s_j, s_abort;
@@ -564,16 +572,16 @@ __global__ __launch_bounds__(256) void k_fps_coop(
     const int wg = blockIdx.x;
     uint32_t *err = &ctl[0];
     const int nmine = (int)((a.nchunk - wg + W - 1) / W);  // chunk slots owned (W <= nchunk)
+    const int ngrp = (nmine + kG - 1) / kG;           // groups of kG slots (slot order is Morton order)
     uint64_t *s_key = (uint64_t *)smem;
-    float *s_bb = (float *)(s_key + nmine);
+    LMask *s_lmask = (LMask *)(s_key + nmine);        // landmarks that can lower a listed chunk
+    LMask *s_gmask = s_lmask + nmine;                 // landmarks that can reach a group
+    float *s_bb = (float *)(s_gmask + ngrp);
     float *s_px = s_bb + 6 * nmine;
     float *s_sec = s_px + 3 * nmine;
     uint32_t *s_list = (uint32_t *)(s_sec + nmine);  // listed chunk slots
-    uint32_t *s_lmask = s_list + nmine;               // and the landmarks that can lower them
-    const int ngrp = (nmine + kG - 1) / kG;           // groups of kG slots (slot order is Morton order)
-    float *s_gbb = (float *)(s_lmask + nmine);        // group boxes (union of the slot boxes)
+    float *s_gbb = (float *)(s_list + nmine);         // group boxes (union of the slot boxes)
     float *s_gkm = s_gbb + 6 * ngrp;                  // group best minima (largest slot minimum)
-    uint32_t *s_gmask = (uint32_t *)(s_gkm + ngrp);   // landmarks that can reach a group
 
     const GridParam g = gp[a.b];
     const int64_t pb = g.pt_base, npts = g.npts;
@@ -609,24 +617,24 @@ __global__ __launch_bounds__(256) void k_fps_coop(
                 const float gb[6] = {s_gbb[gi], s_gbb[ngrp + gi], s_gbb[2 * ngrp + gi],
                                      s_gbb[3 * ngrp + gi], s_gbb[4 * ngrp + gi], s_gbb[5 * ngrp + gi]};
                 const float gkm = s_gkm[gi];
-                uint32_t gm = 0;
+                LMask gm = 0;
                 for (int t = r; t < np; t += q)
-                    gm |= (fps_box_d2(s_pk[t][0], s_pk[t][1], s_pk[t][2], gb) < gkm ? 1u : 0u) << t;
+                    gm |= (LMask)(fps_box_d2(s_pk[t][0], s_pk[t][1], s_pk[t][2], gb) < gkm ? 1u : 0u) << t;
                 if (gm) atomicOr(&s_gmask[gi], gm);
             }
             __syncthreads();
             // b) the slots of reached groups against those landmarks
             for (int s0 = 0; s0 < nmine; s0 += NT) {
                 const int sl = s0 + tid;
-                uint32_t hitm = 0;  // landmarks that can lower this chunk
-                const uint32_t gm = sl < nmine ? s_gmask[sl / kG] : 0u;
+                LMask hitm = 0;  // landmarks that can lower this chunk
+                const LMask gm = sl < nmine ? s_gmask[sl / kG] : (LMask)0;
                 if (gm) {
                     const float bb[6] = {s_bb[sl], s_bb[nmine + sl], s_bb[2 * nmine + sl],
                                          s_bb[3 * nmine + sl], s_bb[4 * nmine + sl], s_bb[5 * nmine + sl]};
                     const float km = __uint_as_float((uint32_t)(s_key[sl] >> 32));
-                    for (uint32_t mk = gm; mk; mk &= mk - 1u) {
-                        const int t = __builtin_ctz(mk);
-                        hitm |= (fps_box_d2(s_pk[t][0], s_pk[t][1], s_pk[t][2], bb) < km ? 1u : 0u) << t;
+                    for (LMask mk = gm; mk; mk &= mk - 1u) {
+                        const int t = __builtin_ctzll((unsigned long long)mk);
+                        hitm |= (LMask)(fps_box_d2(s_pk[t][0], s_pk[t][1], s_pk[t][2], bb) < km ? 1u : 0u) << t;
                     }
                 }
                 const uint64_t mask = __ballot(hitm != 0);
@@ -641,7 +649,7 @@ __global__ __launch_bounds__(256) void k_fps_coop(
             }
             __syncthreads();
             naff = (int)s_n;
-            for (int gi = tid; gi < ngrp; gi += NT) s_gmask[gi] = 0u;  // read again only after later barriers
+            for (int gi = tid; gi < ngrp; gi += NT) s_gmask[gi] = 0;  // read again only after later barriers
         }
         // 2. update them with the landmarks that can lower them (a landmark
         //    whose box bound is not below the chunk's best minimum leaves every
@@ -652,7 +660,7 @@ __global__ __launch_bounds__(256) void k_fps_coop(
             float mm[8];
             int64_t pp[8];
             int sl[U];
-            uint32_t msk[U];
+            LMask msk[U];
 #pragma unroll
             for (int c = 0; c < U; ++c) {
                 const int ee = e0 + c * NW + wid;
@@ -660,7 +668,7 @@ __global__ __launch_bounds__(256) void k_fps_coop(
                 msk[c] = 0;
                 if (ee < naff) {
                     sl[c] = init ? ee : (int)__builtin_amdgcn_readfirstlane(s_list[ee]);
-                    msk[c] = init ? 1u : __builtin_amdgcn_readfirstlane(s_lmask[ee]);
+                    msk[c] = init ? (LMask)1 : uniform_mask(s_lmask[ee]);
                 }
             }
 #pragma unroll
@@ -687,8 +695,8 @@ __global__ __launch_bounds__(256) void k_fps_coop(
                 float d2v[M];
 #pragma unroll
                 for (int u = 0; u < M; ++u) d2v[u] = mm[c * M + u];
-                for (uint32_t mk = msk[c]; mk; mk &= mk - 1u) {
-                    const int t = __builtin_ctz(mk);
+                for (LMask mk = msk[c]; mk; mk &= mk - 1u) {
+                    const int t = __builtin_ctzll((unsigned long long)mk);
                     const float lx = s_pk[t][0], ly = s_pk[t][1], lz = s_pk[t][2];
 #pragma unroll
                     for (int u = 0; u < M; ++u) {
@@ -770,7 +778,7 @@ __global__ __launch_bounds__(256) void k_fps_coop(
                     s_gbb[f * ngrp + gi] = lo;
                     s_gbb[(3 + f) * ngrp + gi] = hi;
                 }
-                s_gmask[gi] = 0u;
+                s_gmask[gi] = 0;
             }
         }
         // 3. this workgroup's three best chunks
@@ -1107,7 +1115,7 @@ static bool coop_shape(int64_t n, int cus, CoopShape *cs) {
             cs->nwg = (int32_t)w;
             cs->lm = l;
             cs->nchunk = nc;
-            cs->shmem = (int)(cpw * 56 + (cpw + kG - 1) / kG * 32);
+            cs->shmem = (int)(cpw * (52 + sizeof(LMask)) + (cpw + kG - 1) / kG * (28 + sizeof(LMask)));
             return true;
         }
     }
