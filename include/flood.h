@@ -78,6 +78,12 @@ const char *flood_last_error(void);
  * EDEGENERATE cannot be detected before the run: if a cloud has fewer
  * distinct points than landmarks, its remaining indices repeat an earlier
  * landmark and its radius reaches 0; callers check radius.
+ * Clouds of at least 2^19 points run as one cooperative launch (one
+ * workgroup per CU exchanging candidates through the workspace); the call
+ * fails with FLOOD_EHIP if the device cannot co-schedule it.  Should the
+ * workgroups stop hearing from each other (a poll limit of about 4M polls
+ * per exchange), the launch ends and the cloud's undecided indices are -1:
+ * callers that cannot rule that out check for negative indices.
  */
 size_t flood_fps_workspace_size(int32_t B, const int64_t *x_off, const int32_t *n_lm);
 flood_status flood_fps(const float *X, int32_t B, const int64_t *x_off, const int64_t *x_off_d,
