@@ -586,7 +586,8 @@ __device__ __forceinline__ int find_cloud(const int64_t *__restrict__ s_off, int
     return lo_b;
 }
 
-static constexpr uint32_t kGrab = 2;    // queue entries a wave takes per atomic
+static constexpr uint32_t kGrab = 4;    // queue entries a wave takes per atomic, at most
+static constexpr uint32_t kGrabSmall = 2;  // for short queues (tail balance); long queues take kGrab (fewer atomics)
 static constexpr uint32_t kSeg = 2048;  // queue segment of one XCD (spatially adjacent open samples)
 
 // queue position of the v-th entry an XCD takes (segments x, x+8, ... of
@@ -610,17 +611,18 @@ __global__ __launch_bounds__(kWaveBlock) __attribute__((amdgpu_waves_per_eu(8, 8
     // queue segments x, x+8, ... through its own counter, so neighbouring
     // samples (same tile, same grid rows) meet in one L2
     const uint32_t xcd = blockIdx.x & 7u;
+    const uint32_t grab = n > (1u << 19) ? kGrab : kGrabSmall;
     while (true) {
         uint32_t v0 = 0;
-        if (lane == 0) v0 = atomicAdd(&queue_next[xcd], kGrab);
+        if (lane == 0) v0 = atomicAdd(&queue_next[xcd], grab);
         v0 = __builtin_amdgcn_readfirstlane(v0);
         if (seg_index(v0, xcd) >= n) break;
-        // lanes 0..kGrab-1 fetch the grabbed entries and their simplices'
+        // lanes 0..grab-1 fetch the grabbed entries and their simplices'
         // running values together (a stale value only retires less)
         float4 qp = make_float4(0.f, 0.f, 0.f, 0.f);
         uint32_t qg = 0, qc = 0;
         float qm = 0.f;
-        if (lane < (int)kGrab) {
+        if (lane < (int)grab) {
             const uint32_t i = seg_index(v0 + lane, xcd);
             if (i < n) {
                 const OpenSample o = queue[i];
@@ -631,7 +633,7 @@ __global__ __launch_bounds__(kWaveBlock) __attribute__((amdgpu_waves_per_eu(8, 8
                 qm = fmaxf(seed[j], key_value(__hip_atomic_load(&key[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)));
             }
         }
-        for (int u = 0; u < (int)kGrab; ++u) {
+        for (int u = 0; u < (int)grab; ++u) {
             if (seg_index(v0 + u, xcd) >= n) break;
             const float sx = __uint_as_float(__builtin_amdgcn_readlane(__float_as_uint(qp.x), u));
             const float sy = __uint_as_float(__builtin_amdgcn_readlane(__float_as_uint(qp.y), u));

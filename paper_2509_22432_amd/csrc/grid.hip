@@ -544,19 +544,16 @@ __global__ __launch_bounds__(kSortBlock) void k_bucket_sort(const GridParam *gp,
     }
 }
 
-// one thread per 32 cells: the occupancy bits
+// one lane per cell: a wave's ballot gives the occupancy bits of its 64
+// consecutive cells, i.e. two words
 __global__ __launch_bounds__(kBlock) void k_occ_bits(const uint32_t *cell_start, int64_t total_cells, uint32_t *occ) {
-    const int64_t w = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    const int64_t c0 = w * 32;
-    if (c0 >= total_cells) return;
-    uint32_t m = 0, prev = cell_start[c0];
-    const int n = (int)(total_cells - c0 < 32 ? total_cells - c0 : 32);
-    for (int i = 0; i < n; ++i) {
-        const uint32_t next = cell_start[c0 + i + 1];
-        m |= (next > prev ? 1u : 0u) << i;
-        prev = next;
+    const int64_t c = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const bool held = c < total_cells && cell_start[c + 1] > cell_start[c];
+    const uint64_t m = __ballot(held);
+    if ((threadIdx.x & 63) == 0 && c < total_cells) {
+        occ[c >> 5] = (uint32_t)m;
+        if (c + 32 < total_cells) occ[(c >> 5) + 1] = (uint32_t)(m >> 32);
     }
-    occ[w] = m;
 }
 
 hipError_t grid_build(const float *X, int32_t B, const int64_t *x_off, const int64_t *x_off_d,
@@ -584,9 +581,8 @@ hipError_t grid_build(const float *X, int32_t B, const int64_t *x_off, const int
     }
     hipLaunchKernelGGL(k_bucket_sort, dim3((unsigned)g.nbtot), dim3(kSortBlock), sh_bucket, s, g.gp, g.bk_off, B,
                        g.shift, g.bstart, g.tmp_pt, g.cell_start, g.xs, g.nbtot, g.total_cells, g.total_pts);
-    const int64_t nw = (g.total_cells + 31) / 32;
-    hipLaunchKernelGGL(k_occ_bits, dim3((unsigned)((nw + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, g.cell_start,
-                       g.total_cells, g.occ);
+    hipLaunchKernelGGL(k_occ_bits, dim3((unsigned)((g.total_cells + kBlock - 1) / kBlock)), dim3(kBlock), 0, s,
+                       g.cell_start, g.total_cells, g.occ);
     return hipGetLastError();
 }
 
