@@ -169,9 +169,10 @@ __global__ __launch_bounds__(kWaveBlock) __attribute__((amdgpu_waves_per_eu(T ==
     unsigned long long *__restrict__ evals, unsigned long long *__restrict__ stats) {
     const int lane = threadIdx.x & 63;
     const int wpb = blockDim.x >> 6;
-    __shared__ float4 s_pt[kWaveBlock / 64][kStage];
+    // staged points, coordinates apart: one 16-byte read gives a coordinate of four points
+    __shared__ __align__(16) float s_px[kWaveBlock / 64][3][kStage];
     __shared__ uint32_t s_p0[kWaveBlock / 64][64], s_end[kWaveBlock / 64][64];
-    float4 *sw_pt = s_pt[threadIdx.x >> 6];
+    float *sw_x = s_px[threadIdx.x >> 6][0], *sw_y = s_px[threadIdx.x >> 6][1], *sw_z = s_px[threadIdx.x >> 6][2];
     uint32_t *sw_p0 = s_p0[threadIdx.x >> 6], *sw_end = s_end[threadIdx.x >> 6];
     // wave-uniform by construction; readfirstlane lets the compiler keep the
     // tile state in scalar registers
@@ -364,18 +365,23 @@ __global__ __launch_bounds__(kWaveBlock) __attribute__((amdgpu_waves_per_eu(T ==
                         if (b0 + kStage < total) fetch(b0 + kStage, cn);
                         __builtin_amdgcn_wave_barrier();
 #pragma unroll
-                        for (int u = 0; u < kStage / 64; ++u) sw_pt[u * 64 + lane] = cc[u];
+                        for (int u = 0; u < kStage / 64; ++u) {
+                            sw_x[u * 64 + lane] = cc[u].x;
+                            sw_y[u * 64 + lane] = cc[u].y;
+                            sw_z[u * 64 + lane] = cc[u].z;
+                        }
                         __builtin_amdgcn_wave_barrier();
                         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
                         const int n4 = (int)((min(total - b0, (uint32_t)kStage) + 3u) & ~3u);
                         for (int j = 0; j < n4; j += 4) {
-                            const float4 c0 = sw_pt[j], c1 = sw_pt[j + 1], c2 = sw_pt[j + 2], c3 = sw_pt[j + 3];
+                            const float4 px = *(const float4 *)&sw_x[j], py = *(const float4 *)&sw_y[j],
+                                         pz = *(const float4 *)&sw_z[j];
 #pragma unroll
                             for (int t = 0; t < T; ++t) {
-                                const float d0 = dist2(sx[t], sy[t], sz[t], c0.x, c0.y, c0.z);
-                                const float d1 = dist2(sx[t], sy[t], sz[t], c1.x, c1.y, c1.z);
-                                const float d2 = dist2(sx[t], sy[t], sz[t], c2.x, c2.y, c2.z);
-                                const float d3 = dist2(sx[t], sy[t], sz[t], c3.x, c3.y, c3.z);
+                                const float d0 = dist2(sx[t], sy[t], sz[t], px.x, py.x, pz.x);
+                                const float d1 = dist2(sx[t], sy[t], sz[t], px.y, py.y, pz.y);
+                                const float d2 = dist2(sx[t], sy[t], sz[t], px.z, py.z, pz.z);
+                                const float d3 = dist2(sx[t], sy[t], sz[t], px.w, py.w, pz.w);
                                 best[t] = fminf(fminf(best[t], fminf(d0, d1)), fminf(d2, d3));
                             }
                         }
