@@ -41,7 +41,7 @@ flood_tuning default_tuning(const flood_tuning *t) {
     r.cells_per_point = 1.0f;
     r.samples_per_lane = 1;
     r.waves_per_block = 4;
-    r.tile_shells = 2;
+    r.tile_shells = 4;
     r.tile_extent = 16;
     if (t) {
         if (t->cells_per_point != 0) r.cells_per_point = t->cells_per_point;
