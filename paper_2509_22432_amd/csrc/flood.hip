@@ -456,8 +456,9 @@ __global__ __launch_bounds__(kWaveBlock) __attribute__((amdgpu_waves_per_eu(T ==
 // phase B: one wavefront per open sample.  The lanes take the rows (y,z) of
 // the grid in Chebyshev rings around the sample's cell, 64 rows per round
 // trip; each row contributes the x-range that can beat the current bound,
-// the rows' points are flattened over the lanes and every lane keeps the
-// lexicographic minimum (d^2, point row); a wave reduction after every step
+// the rows' points are flattened over the lanes and every lane keeps its
+// minimum d^2 (the winner search, which reuses the walk, keeps the
+// lexicographic minimum (d^2, point row)); a wave reduction after every step
 // shares the bound.  (Wider steps scan more points: the rows of one step
 // share the bound from its start.)  Ring r cannot hold a point closer than
 // (r-1) h, which ends the search.
@@ -496,8 +497,11 @@ __device__ __forceinline__ void lex_min(float &bd, int32_t &bi, float od, int32_
 // holds the same sample).  On return (bd, bi) is the lexicographic minimum
 // (squared distance, point row) over all points with distance^2 <= the
 // initial bd, unless `retire` is set and the bound fell below M (then the
-// function returns true early and (bd, bi) is only an upper bound).
+// function returns true early and (bd, bi) is only an upper bound).  With
+// kIdx false only bd is kept (the flooding search needs the distance alone)
+// and bi is left as it was.
 // s_p0 / s_end: 64 entries of LDS per wave.
+template <bool kIdx>
 __device__ bool ring_search(const GridParam &g, const uint32_t *__restrict__ cs, const uint32_t *__restrict__ occ,
                             const float4 *__restrict__ xs,
                             float sx, float sy, float sz, float &bd, int32_t &bi, bool retire, float &M,
@@ -565,14 +569,21 @@ __device__ bool ring_search(const GridParam &g, const uint32_t *__restrict__ cs,
                 if (pp[u] != 0xffffffffu) cc[u] = xs[pp[u]];
 #pragma unroll
             for (int u = 0; u < kU; ++u)
-                if (pp[u] != 0xffffffffu)
-                    lex_min(lbd, lbi, dist2(sx, sy, sz, cc[u].x, cc[u].y, cc[u].z), __float_as_int(cc[u].w));
+                if (pp[u] != 0xffffffffu) {
+                    const float d2 = dist2(sx, sy, sz, cc[u].x, cc[u].y, cc[u].z);
+                    if (kIdx) lex_min(lbd, lbi, d2, __float_as_int(cc[u].w));
+                    else lbd = fminf(lbd, d2);
+                }
         }
         __builtin_amdgcn_wave_barrier();
-        uint32_t mmin;  // distances are non-negative: float order is bit order
-        const int src = wave_argmin_pair(__float_as_uint(lbd), (uint32_t)lbi, mmin);
-        bd = __uint_as_float(mmin);
-        bi = (int32_t)rd_lane((uint32_t)lbi, src);
+        if (kIdx) {
+            uint32_t mmin;  // distances are non-negative: float order is bit order
+            const int src = wave_argmin_pair(__float_as_uint(lbd), (uint32_t)lbi, mmin);
+            bd = __uint_as_float(mmin);
+            bi = (int32_t)rd_lane((uint32_t)lbi, src);
+        } else {
+            bd = wave_min_f32_dpp(lbd);
+        }
         if (retire) {
             if ((base & 511) == 448)
                 M = fmaxf(M, key_value(__hip_atomic_load(keyj, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)));
@@ -651,7 +662,7 @@ __global__ __launch_bounds__(kWaveBlock) __attribute__((amdgpu_waves_per_eu(8, 8
             const int64_t j = gid / (uint32_t)a.n_int;
             const int q = (int)(gid % (uint32_t)a.n_int);
             int32_t bi = 0x7fffffff;
-            const bool retired = ring_search(g, cs, occ, xs, sx, sy, sz, bd, bi, a.d > 0, M, &key[j], s_p0[wid],
+            const bool retired = ring_search<false>(g, cs, occ, xs, sx, sy, sz, bd, bi, a.d > 0, M, &key[j], s_p0[wid],
                                              s_end[wid], lane, nev);
             if (!retired && lane == 0) publish(key, seed, (int32_t)j, q, bd, a.d == 0);
         }
@@ -690,7 +701,7 @@ __global__ __launch_bounds__(kWaveBlock) void k_winner_search(
     float M = 0.f;
     unsigned long long nev = 0;
     const GridParam g = gp[find_cloud(s_off, B, j)];
-    ring_search(g, cs, occ, xs, sx, sy, sz, bd, bi, false, M, nullptr, s_p0[wid], s_end[wid], lane, nev);
+    ring_search<true>(g, cs, occ, xs, sx, sy, sz, bd, bi, false, M, nullptr, s_p0[wid], s_end[wid], lane, nev);
     if (lane == 0) win_x[j] = bi;
 }
 
