@@ -250,6 +250,11 @@ __global__ __launch_bounds__(kWaveBlock) __attribute__((amdgpu_waves_per_eu(T ==
         hi[ax] = __builtin_amdgcn_readfirstlane(hi[ax]);
     }
     unsigned long long nev = 0;
+    // lanes [0, grp) hold the tile's samples; with grp < 64 (one sample per
+    // lane only) lane l holds a copy of lane l mod grp's sample and scans its
+    // share of every staged pass, and the copies' minima are combined after
+    // each shell
+    int grp = 64;
     const bool any_live = hi[0] >= 0;
     const bool compact = any_live && hi[0] - lo[0] < a.max_extent && hi[1] - lo[1] < a.max_extent &&
                          hi[2] - lo[2] < a.max_extent && a.radius_budget >= 0;
@@ -334,7 +339,7 @@ __global__ __launch_bounds__(kWaveBlock) __attribute__((amdgpu_waves_per_eu(T ==
                     sw_end[lane] = incl;
                     int nlive = 0;
 #pragma unroll
-                    for (int t = 0; t < T; ++t) nlive += __popcll(__ballot(live[t]));
+                    for (int t = 0; t < T; ++t) nlive += __popcll(__ballot(live[t] && lane < grp));
                     nev += (unsigned long long)total * (unsigned long long)nlive;
                     __builtin_amdgcn_wave_barrier();
                     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -373,7 +378,7 @@ __global__ __launch_bounds__(kWaveBlock) __attribute__((amdgpu_waves_per_eu(T ==
                         __builtin_amdgcn_wave_barrier();
                         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
                         const int n4 = (int)((min(total - b0, (uint32_t)kStage) + 3u) & ~3u);
-                        for (int j = 0; j < n4; j += 4) {
+                        auto eval4 = [&](int j) {
                             const float4 px = *(const float4 *)&sw_x[j], py = *(const float4 *)&sw_y[j],
                                          pz = *(const float4 *)&sw_z[j];
 #pragma unroll
@@ -384,10 +389,21 @@ __global__ __launch_bounds__(kWaveBlock) __attribute__((amdgpu_waves_per_eu(T ==
                                 const float d3 = dist2(sx[t], sy[t], sz[t], px.w, py.w, pz.w);
                                 best[t] = fminf(fminf(best[t], fminf(d0, d1)), fminf(d2, d3));
                             }
+                        };
+                        if (grp == 64) {
+                            for (int j = 0; j < n4; j += 4) eval4(j);
+                        } else {
+                            // copy c = lane / grp takes the groups of four c, c + 64/grp, ...
+                            const int jstep = 256 / grp;
+                            for (int j = 4 * (lane / grp); j < n4; j += jstep) eval4(j);
                         }
                         __builtin_amdgcn_wave_barrier();
                     }
                 }
+            }
+            if (T == 1 && grp < 64) {
+                // the copies' minima: lanes l and l ^ o (o >= grp) hold the same sample
+                for (int o = grp; o < 64; o <<= 1) best[0] = fminf(best[0], __shfl_xor(best[0], o, 64));
             }
             // completion and retirement
             const bool full = lo[0] == 0 && lo[1] == 0 && lo[2] == 0 && hi[0] == g.nx - 1 && hi[1] == g.ny - 1 &&
@@ -411,7 +427,7 @@ __global__ __launch_bounds__(kWaveBlock) __attribute__((amdgpu_waves_per_eu(T ==
                     // exact minimum: publish (value, rank); x* is found later
                     // for the winning sample only
                     live[t] = false;
-                    publish(key, seed, sj[t], sq[t], best[t], d == 0);
+                    if (lane < grp) publish(key, seed, sj[t], sq[t], best[t], d == 0);
                 } else {
                     const uint64_t kv = __hip_atomic_load(&key[sj[t]], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                     M[t] = fmaxf(M[t], key_value(kv));
@@ -419,7 +435,40 @@ __global__ __launch_bounds__(kWaveBlock) __attribute__((amdgpu_waves_per_eu(T ==
                 }
                 anylive |= live[t];
             }
+            if (T == 1 && grp < 64) {
+                // the copies follow their sample's own lane (the running
+                // values they loaded may differ)
+                const int c = lane & (grp - 1);
+                live[0] = __shfl((int)live[0], c, 64) != 0;
+                M[0] = __shfl(M[0], c, 64);
+                anylive = live[0];
+            }
             if (!__any(anylive) || full || r >= a.radius_budget) break;
+            if (T == 1) {
+                // at most half the samples still open: gather them into the
+                // lowest lanes and give each 64 / grp copies
+                const uint64_t lm = __ballot(live[0] && lane < grp);
+                const int n = __popcll(lm);
+                int ng = 2;
+                while (ng < n) ng <<= 1;
+                if (ng < grp) {
+                    if (live[0] && lane < grp) sw_p0[__popcll(lm & ((1ull << lane) - 1ull))] = (uint32_t)lane;
+                    __builtin_amdgcn_wave_barrier();
+                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                    const int idx = lane & (ng - 1);
+                    const int src = idx < n ? (int)sw_p0[idx] : 0;
+                    __builtin_amdgcn_wave_barrier();
+                    sx[0] = __shfl(sx[0], src, 64);
+                    sy[0] = __shfl(sy[0], src, 64);
+                    sz[0] = __shfl(sz[0], src, 64);
+                    best[0] = __shfl(best[0], src, 64);
+                    M[0] = __shfl(M[0], src, 64);
+                    sj[0] = __shfl(sj[0], src, 64);
+                    sq[0] = __shfl(sq[0], src, 64);
+                    live[0] = idx < n;
+                    grp = ng;
+                }
+            }
             for (int ax = 0; ax < 3; ++ax) {
                 olo[ax] = lo[ax];
                 ohi[ax] = hi[ax];
@@ -432,7 +481,7 @@ __global__ __launch_bounds__(kWaveBlock) __attribute__((amdgpu_waves_per_eu(T ==
     // open samples go to phase B with their bound
 #pragma unroll
     for (int t = 0; t < T; ++t) {
-        const bool push = live[t];
+        const bool push = live[t] && lane < grp;
         const uint64_t m = __ballot(push);
         if (!m) continue;
         uint32_t base = 0;
