@@ -216,7 +216,7 @@ typedef struct {
  * uniform-grid cells per point, 0.05..64), samples_per_lane (1, 2 or 4),
  * waves_per_block (1..4), tile_shells (cell shells a wave scans
  * cooperatively around its samples before handing open samples to the
- * per-sample search, 1..8, default 4; -1 sends every sample to the
+ * per-sample search, 1..32, default 6; -1 sends every sample to the
  * per-sample search),
  * tile_extent (a tile whose samples span more cells than this along an axis
  * skips the cooperative search, 2..64). */

@@ -17,14 +17,14 @@ import torch
 from . import api
 
 DEFAULT_CANDIDATES = [
-    {"cells_per_point": 1.0, "samples_per_lane": 1, "waves_per_block": 4, "tile_shells": 4, "tile_extent": 8},
-    {"cells_per_point": 1.0, "samples_per_lane": 1, "waves_per_block": 4, "tile_shells": 4, "tile_extent": 24},
-    {"cells_per_point": 1.0, "samples_per_lane": 1, "waves_per_block": 4, "tile_shells": 4},
-    {"cells_per_point": 0.5, "samples_per_lane": 1, "waves_per_block": 4, "tile_shells": 4},
-    {"cells_per_point": 2.0, "samples_per_lane": 1, "waves_per_block": 4, "tile_shells": 4},
-    {"cells_per_point": 1.0, "samples_per_lane": 2, "waves_per_block": 4, "tile_shells": 4},
-    {"cells_per_point": 1.0, "samples_per_lane": 1, "waves_per_block": 4, "tile_shells": 2},
+    {"cells_per_point": 1.0, "samples_per_lane": 1, "waves_per_block": 4, "tile_shells": 6, "tile_extent": 8},
+    {"cells_per_point": 1.0, "samples_per_lane": 1, "waves_per_block": 4, "tile_shells": 6, "tile_extent": 24},
     {"cells_per_point": 1.0, "samples_per_lane": 1, "waves_per_block": 4, "tile_shells": 6},
+    {"cells_per_point": 0.5, "samples_per_lane": 1, "waves_per_block": 4, "tile_shells": 6},
+    {"cells_per_point": 2.0, "samples_per_lane": 1, "waves_per_block": 4, "tile_shells": 6},
+    {"cells_per_point": 1.0, "samples_per_lane": 2, "waves_per_block": 4, "tile_shells": 6},
+    {"cells_per_point": 1.0, "samples_per_lane": 1, "waves_per_block": 4, "tile_shells": 4},
+    {"cells_per_point": 1.0, "samples_per_lane": 1, "waves_per_block": 4, "tile_shells": 8},
     {"cells_per_point": 1.0, "samples_per_lane": 1, "waves_per_block": 4, "tile_shells": -1},
 ]
 

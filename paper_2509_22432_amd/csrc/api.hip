@@ -41,7 +41,7 @@ flood_tuning default_tuning(const flood_tuning *t) {
     r.cells_per_point = 1.0f;
     r.samples_per_lane = 1;
     r.waves_per_block = 4;
-    r.tile_shells = 4;
+    r.tile_shells = 6;
     r.tile_extent = 16;
     if (t) {
         if (t->cells_per_point != 0) r.cells_per_point = t->cells_per_point;
@@ -59,8 +59,8 @@ flood_status check_tuning(const flood_tuning &t) {
     if (t.samples_per_lane != 1 && t.samples_per_lane != 2 && t.samples_per_lane != 4)
         return fail(FLOOD_EINVAL, "tuning: samples_per_lane must be 1, 2 or 4");
     if (t.waves_per_block < 1 || t.waves_per_block > 4) return fail(FLOOD_EINVAL, "tuning: waves_per_block outside [1, 4]");
-    if (t.tile_shells < -1 || t.tile_shells > 8 || t.tile_shells == 0)
-        return fail(FLOOD_EINVAL, "tuning: tile_shells must be -1 or in [1, 8]");
+    if (t.tile_shells < -1 || t.tile_shells > 32 || t.tile_shells == 0)
+        return fail(FLOOD_EINVAL, "tuning: tile_shells must be -1 or in [1, 32]");
     if (t.tile_extent < 2 || t.tile_extent > 64) return fail(FLOOD_EINVAL, "tuning: tile_extent outside [2, 64]");
     return FLOOD_OK;
 }
