@@ -28,6 +28,7 @@
 namespace flood {
 
 static constexpr int kWaveBlock = 256;
+static constexpr uint32_t kFineMin = 8;  // shortest cell run the tile search tests against every sample
 static constexpr int kU = 4;  // points per lane per step in the per-sample search
 static constexpr int kStage = 128;  // points staged in LDS per pass of the tile search
 
@@ -312,7 +313,9 @@ __global__ __launch_bounds__(kWaveBlock) __attribute__((amdgpu_waves_per_eu(T ==
                         ok = gx * gx + gy * gy + gz * gz < bmax;
                     }
                     // fine: keep a run only if some live sample's bound reaches its box
-                    uint64_t mask = __ballot(ok), need_m = 0;
+                    // (a run shorter than kFineMin points is kept: testing it costs more
+                    // than scanning it)
+                    uint64_t mask = __ballot(ok && p1 - p0 >= kFineMin), need_m = __ballot(ok && p1 - p0 < kFineMin);
                     while (mask) {
                         const int src = __ffsll((unsigned long long)mask) - 1;
                         mask &= mask - 1;
