@@ -219,7 +219,7 @@ typedef struct {
  * per-sample search, 1..32, default 6; -1 sends every sample to the
  * per-sample search),
  * tile_extent (a tile whose samples span more cells than this along an axis
- * skips the cooperative search, 2..64). */
+ * skips the cooperative search, 2..64, default 24). */
 typedef struct {
     float cells_per_point;
     int32_t samples_per_lane;

@@ -18,7 +18,7 @@ from . import api
 
 DEFAULT_CANDIDATES = [
     {"cells_per_point": 1.0, "samples_per_lane": 1, "waves_per_block": 4, "tile_shells": 6, "tile_extent": 8},
-    {"cells_per_point": 1.0, "samples_per_lane": 1, "waves_per_block": 4, "tile_shells": 6, "tile_extent": 24},
+    {"cells_per_point": 1.0, "samples_per_lane": 1, "waves_per_block": 4, "tile_shells": 6, "tile_extent": 16},
     {"cells_per_point": 1.0, "samples_per_lane": 1, "waves_per_block": 4, "tile_shells": 6},
     {"cells_per_point": 0.5, "samples_per_lane": 1, "waves_per_block": 4, "tile_shells": 6},
     {"cells_per_point": 2.0, "samples_per_lane": 1, "waves_per_block": 4, "tile_shells": 6},

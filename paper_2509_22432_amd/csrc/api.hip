@@ -42,7 +42,7 @@ flood_tuning default_tuning(const flood_tuning *t) {
     r.samples_per_lane = 1;
     r.waves_per_block = 4;
     r.tile_shells = 6;
-    r.tile_extent = 16;
+    r.tile_extent = 24;
     if (t) {
         if (t->cells_per_point != 0) r.cells_per_point = t->cells_per_point;
         if (t->samples_per_lane != 0) r.samples_per_lane = t->samples_per_lane;

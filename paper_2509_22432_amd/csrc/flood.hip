@@ -714,8 +714,8 @@ __global__ __launch_bounds__(kWaveBlock) __attribute__((amdgpu_waves_per_eu(8, 8
             const int64_t j = gid / (uint32_t)a.n_int;
             const int q = (int)(gid % (uint32_t)a.n_int);
             int32_t bi = 0x7fffffff;
-            const bool retired = ring_search<false>(g, cs, occ, xs, sx, sy, sz, bd, bi, a.d > 0, M, &key[j], s_p0[wid],
-                                             s_end[wid], lane, nev);
+            const bool retired = ring_search<false>(g, cs, occ, xs, sx, sy, sz, bd, bi, a.d > 0, M, &key[j],
+                                                    s_p0[wid], s_end[wid], lane, nev);
             if (!retired && lane == 0) publish(key, seed, (int32_t)j, q, bd, a.d == 0);
         }
     }
