@@ -390,7 +390,8 @@ __global__ __launch_bounds__(kWaveBlock) __attribute__((amdgpu_waves_per_eu(T ==
                                 const float d1 = dist2(sx[t], sy[t], sz[t], px.y, py.y, pz.y);
                                 const float d2 = dist2(sx[t], sy[t], sz[t], px.z, py.z, pz.z);
                                 const float d3 = dist2(sx[t], sy[t], sz[t], px.w, py.w, pz.w);
-                                best[t] = fminf(fminf(best[t], fminf(d0, d1)), fminf(d2, d3));
+                                best[t] = fminf(fminf(best[t], d0), d1);  // two v_min3
+                                best[t] = fminf(fminf(best[t], d2), d3);
                             }
                         };
                         if (grp == 64) {
