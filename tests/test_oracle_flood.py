@@ -192,3 +192,102 @@ def test_circle_edge_sagitta():
         arcs = (np.diff(np.concatenate([ang, [2 * np.pi]])))
         f, _, _ = FL.flood_dim(X, X, E, 1, 4)
         assert np.allclose(f, 1 - np.cos(arcs / 2), atol=1e-7)
+
+
+# ---------------------------------------------------------------------------
+# diam(X): every parity tolerance is 1e-5 * diam(X), so the oracle's diameter
+# is pinned against brute force and shapes whose diameter is known.
+
+def _diam_brute(X):
+    X = np.asarray(X, np.float64)
+    best = 0.0
+    for i in range(len(X)):
+        best = max(best, float(np.sqrt(((X[i] - X) ** 2).sum(1)).max()))
+    return best
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_diameter_equals_brute_force(seed):
+    rng = np.random.default_rng(100 + seed)
+    clouds = [rng.random((300, 3)), rng.normal(size=(257, 3)) * [1.0, 0.3, 0.05],
+              synth.config_cloud(1, n_points=400).astype(np.float64)]
+    for X in clouds:
+        assert abs(FL.diameter(X) - _diam_brute(X)) <= 1e-15 * _diam_brute(X)
+
+
+def test_diameter_known_shapes():
+    cube = np.array([[i, j, k] for i in (0, 1) for j in (0, 1) for k in (0, 1)], np.float64)
+    assert abs(FL.diameter(cube) - np.sqrt(3.0)) <= 1e-15
+    # collinear points (no hull): the two ends
+    seg = np.outer(np.linspace(0.0, 2.5, 11), [0.6, 0.0, 0.8])
+    assert abs(FL.diameter(seg) - 2.5) <= 1e-14
+    # a sphere sample containing an antipodal pair: 2 r
+    rng = np.random.default_rng(5)
+    v = rng.normal(size=(200, 3))
+    v /= np.linalg.norm(v, axis=1, keepdims=True)
+    v[0], v[1] = [0, 0, 1], [0, 0, -1]
+    assert abs(FL.diameter(0.7 * v) - 1.4) <= 1e-14
+    # fewer than four points, and a single point
+    assert abs(FL.diameter(cube[[0, 7]]) - np.sqrt(3.0)) <= 1e-15
+    assert FL.diameter(cube[:1]) == 0.0
+    # exact power-of-two scaling
+    X = np.random.default_rng(6).random((100, 3))
+    assert FL.diameter(4.0 * X) == 4.0 * FL.diameter(X)
+
+
+def test_diameter_of_the_torus_workload():
+    # R = 1, r = 0.3: the outer equator has diameter 2 (R + r) = 2.6; the
+    # noise (sigma = 0.01) moves it by a few sigma at most
+    X = synth.config_cloud(1)
+    assert 2.6 - 0.02 <= FL.diameter(X) <= 2.6 + 0.06
+
+
+# ---------------------------------------------------------------------------
+# Lemma 6 covering radius h(sigma), pinned from both sides: it must bound the
+# grid's true covering radius (max over conv sigma of the distance to the
+# nearest grid point), and on an edge and an equilateral triangle it exceeds
+# it by exactly the factors 2 and 3 (closed forms of the 1-D grid and of the
+# triangular lattice, whose covering radius is the small triangles'
+# circumradius (l/k)/sqrt 3).
+
+def _grid_cover_radius(V, k, n_probe):
+    d = len(V) - 1
+    A = FL.samples(d, k).astype(np.float64) / k
+    G = A @ V
+    rng = np.random.default_rng(9)
+    lam = rng.dirichlet(np.ones(d + 1), n_probe)
+    # dense probes plus the centroids of the grid's small cells
+    fine = [FL.samples(d, m * k).astype(np.float64) / (m * k) for m in (3, 4)]
+    P = np.concatenate([lam] + fine) @ V
+    best = 0.0
+    for i in range(0, len(P), 4096):
+        dd = np.sqrt(((P[i:i + 4096, None, :] - G[None]) ** 2).sum(-1)).min(1)
+        best = max(best, float(dd.max()))
+    return best
+
+
+def test_h_grid_closed_forms():
+    for k in (1, 2, 3, 5, 8):
+        e = np.array([[0.1, 0.2, 0.3], [1.3, -0.4, 0.5]])
+        length = np.linalg.norm(e[1] - e[0])
+        h = FL.h_grid(e, np.array([[0, 1]]), k)[0]
+        assert abs(h - length / k) <= 1e-14
+        assert abs(h - 2 * _grid_cover_radius(e, k, 2000)) <= 1e-12
+        tri = np.array([[0, 0, 0], [1, 0, 0], [0.5, np.sqrt(3) / 2, 0]]) * 0.75 + [0.2, 0.1, -0.3]
+        h = FL.h_grid(tri, np.array([[0, 1, 2]]), k)[0]
+        cov = _grid_cover_radius(tri, k, 20000)
+        assert abs(h - 3 * cov) <= 1e-12
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_h_grid_bounds_true_cover(seed):
+    rng = np.random.default_rng(40 + seed)
+    for d in (1, 2, 3):
+        V = rng.random((d + 1, 3))
+        for k in (2, 4):
+            h = FL.h_grid(V, np.arange(d + 1).reshape(1, -1), k)[0]
+            cov = _grid_cover_radius(V, k, 20000)
+            assert cov <= h * (1 + 1e-12)
+            # and between the longest edge over k and sqrt(#edges) times it
+            emax = max(np.linalg.norm(V[i] - V[j]) for i in range(d + 1) for j in range(i))
+            assert emax / k <= h * (1 + 1e-12) <= np.sqrt(d * (d + 1) / 2) * emax / k * (1 + 1e-12)
