@@ -241,3 +241,127 @@ def nearest(X, P):
         out_i[i:i + 256] = np.argmin(d, axis=1)
         out_d[i:i + 256] = np.sqrt(d[np.arange(len(d)), out_i[i:i + 256]])
     return out_d, out_i
+
+
+# ---------------------------------------------------------------------------
+# Random sample sets (Thm. 5 for any P_sigma inside conv sigma; Lemma 9 for
+# uniform draws).  Each simplex of dimension >= 1 owns m points drawn from
+# its convex hull by a counter-based generator (see flood_oracle.c); each
+# face has its own set, so the closure over faces is load-bearing.
+
+
+def philox4x64_10(ctr, key):
+    """The raw generator of the C part: 4 words for counter `ctr` (4 uint64)
+    and key `key` (2 uint64)."""
+    c = np.ascontiguousarray(ctr, dtype=np.uint64)
+    k = np.ascontiguousarray(key, dtype=np.uint64)
+    out = np.zeros(4, np.uint64)
+    native.lib().or_philox4x64_10(native.ptr(c), native.ptr(k), native.ptr(out))
+    return out
+
+
+def random_weights(d: int, q: int, row: int, seed: int) -> np.ndarray:
+    """Barycentric weights (d+1 entries) of random sample q of the simplex in
+    cloud-local row `row` of dimension d."""
+    w = np.zeros(4, np.float64)
+    native.lib().or_random_weights(d, q, row, seed, native.ptr(w))
+    return w[:d + 1].copy()
+
+
+def flood_random_dim(X, Lxyz, simp, d: int, m: int, seed: int, rows=None, mode: str = "brute", xsorted=None,
+                     nthreads=None, counter=None):
+    """Own value of each d-simplex under random sample sets (max over its m
+    samples of d(p, X); vertices: the vertex), without the face closure.
+    rows: the simplices' cloud-local rows (default 0..n-1).  Returns
+    (f float64 [n], win_q int32 [n], win_x int32 [n])."""
+    X = _as_f64(X)
+    Lxyz = _as_f64(Lxyz)
+    simp = np.ascontiguousarray(simp, dtype=np.int32).reshape(-1, d + 1)
+    n = simp.shape[0]
+    rows = np.arange(n, dtype=np.int64) if rows is None else np.ascontiguousarray(rows, dtype=np.int64)
+    f = np.zeros(n, np.float64)
+    wq = np.zeros(n, np.int32)
+    wx = np.zeros(n, np.int32)
+    if n == 0:
+        return f, wq, wx
+    md = {"brute": 0, "masked": 1}[mode]
+    if md == 1 and xsorted is None:
+        xsorted = XSorted(X)
+    xs = xsorted.xs if md == 1 else X
+    order = xsorted.order if md == 1 else np.zeros(1, np.int64)
+    rc = native.lib().or_flood_random(native.ptr(X), X.shape[0], native.ptr(Lxyz), native.ptr(simp),
+                                      native.ptr(rows), n, d, m, seed, md, native.ptr(xs), native.ptr(order),
+                                      native.ptr(f), native.ptr(wq), native.ptr(wx),
+                                      native.ptr(counter) if counter is not None else None,
+                                      native.threads(nthreads))
+    if rc != 0:
+        raise ValueError("or_flood_random failed: %d" % rc)
+    return f, wq, wx
+
+
+def flood_random_all(X, Lxyz, cx, m: int, seed: int, mode: str = "brute", nthreads=None):
+    """Own values of every simplex under random sample sets: {d: (f, win_q,
+    win_x)}; apply `closure` for the filtration."""
+    Lxyz = _as_f64(Lxyz)
+    xsorted = XSorted(X) if mode == "masked" else None
+    simp = {0: np.arange(Lxyz.shape[0]).reshape(-1, 1), 1: cx["E"], 2: cx["F"], 3: cx["T"]}
+    return {d: flood_random_dim(X, Lxyz, simp[d], d, m, seed, None, mode, xsorted, nthreads) for d in range(4)}
+
+
+def random_winners(vals, cx):
+    """For the closure f(sigma) = max(own(sigma), max over facets f(tau)):
+    the simplex (dimension, row) that owns the winning sample of every
+    simplex -- its own sample when own >= the facets' max, else the first
+    facet (omitting vertex i, i ascending) attaining the max, followed down.
+    Returns {d: (owner_dim [n], owner_row [n])}."""
+    f = closure(vals, cx)
+    facets = {1: None, 2: cx["tri_edges"], 3: cx["tet_tris"]}
+    own = {}
+    own[0] = (np.zeros(len(f[0]), np.int64), np.arange(len(f[0]), dtype=np.int64))
+    for d in (1, 2, 3):
+        n = len(f[d])
+        od = np.full(n, d, np.int64)
+        orow = np.arange(n, dtype=np.int64)
+        for j in range(n):
+            if vals[d][0][j] >= f[d][j]:
+                continue
+            if d == 1:
+                fac = [cx["E"][j][1], cx["E"][j][0]]  # facet i omits vertex i
+            else:
+                fac = list(facets[d][j])
+            for i, t in enumerate(fac):
+                if f[d - 1][t] == f[d][j]:
+                    od[j], orow[j] = own[d - 1][0][t], own[d - 1][1][t]
+                    break
+        own[d] = (od, orow)
+    return own
+
+
+def random_gradient(X, Lxyz, cx, vals, m, seed, weights):
+    """Analytic gradient of loss = sum_sigma w_sigma f(sigma) under random
+    sample sets: the winning sample s* = sum_i w*_i v_i belongs to the owner
+    simplex (random_winners), x* is its nearest point; dL/dx* -= w u,
+    dL/dv_i += w w*_i u over the owner's vertices, u = (s* - x*)/f."""
+    X = _as_f64(X)
+    Lxyz = _as_f64(Lxyz)
+    gX = np.zeros_like(X)
+    gL = np.zeros_like(Lxyz)
+    simp = {0: np.arange(Lxyz.shape[0]).reshape(-1, 1), 1: cx["E"], 2: cx["F"], 3: cx["T"]}
+    f = closure(vals, cx)
+    own = random_winners(vals, cx)
+    for d in range(4):
+        w = np.asarray(weights[d], dtype=np.float64)
+        for j in range(len(f[d])):
+            if w[j] == 0.0 or f[d][j] <= 0.0:
+                continue
+            od, orow = int(own[d][0][j]), int(own[d][1][j])
+            q = int(vals[od][1][orow])
+            xi = int(vals[od][2][orow])
+            bw = random_weights(od, q, orow, seed)
+            vv = simp[od][orow]
+            sp = (bw[:, None] * Lxyz[vv]).sum(0)
+            u = (sp - X[xi]) / f[d][j]
+            gX[xi] -= w[j] * u
+            for i in range(od + 1):
+                gL[vv[i]] += w[j] * bw[i] * u
+    return gX, gL

@@ -22,6 +22,17 @@ def lib():
                                ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                                ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int]
+        L.or_flood_random.restype = ctypes.c_int
+        L.or_flood_random.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
+                                      ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32,
+                                      ctypes.c_uint64, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
+                                      ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                      ctypes.c_int]
+        L.or_random_weights.restype = None
+        L.or_random_weights.argtypes = [ctypes.c_int32, ctypes.c_int64, ctypes.c_int64, ctypes.c_uint64,
+                                        ctypes.c_void_p]
+        L.or_philox4x64_10.restype = None
+        L.or_philox4x64_10.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
         L.or_max_threads.restype = ctypes.c_int
         L.or_count_samples.restype = ctypes.c_int64
         L.or_count_samples.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p]
