@@ -197,3 +197,34 @@ def lattice_points(side: int, seed: int = 7) -> np.ndarray:
     g = np.arange(side, dtype=np.float32)
     X = np.stack(np.meshgrid(g, g, g, indexing="ij"), -1).reshape(-1, 3)
     return np.ascontiguousarray(X[np.random.default_rng(seed).permutation(len(X))])
+
+
+def swisscheese(n_points: int = 1_000_000, n_voids: int = 10, seed: int = 2000, side: float = 5.0):
+    """A swiss-cheese cloud as the paper's synthetic classification dataset
+    is described (Sec. 5.3): points uniform in [0, side]^3 minus n_voids
+    disjoint balls with radii uniform in [0.1, 0.5] and uniform centres (each
+    ball inside the cube; a ball overlapping an earlier one is redrawn).
+    Returns (float32 [n_points, 3], centres [n_voids, 3], radii [n_voids])."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    cs, rs = [], []
+    while len(cs) < n_voids:
+        r = rng.uniform(0.1, 0.5)
+        c = rng.uniform(r, side - r, 3)
+        if all(np.linalg.norm(c - c2) > r + r2 for c2, r2 in zip(cs, rs)):
+            cs.append(c)
+            rs.append(r)
+    C = np.array(cs).reshape(-1, 3)
+    R = np.array(rs)
+    out = []
+    have = 0
+    while have < n_points:
+        m = int((n_points - have) * 1.05) + 64
+        p = rng.random((m, 3)) * side
+        keep = np.ones(m, dtype=bool)
+        for c, r in zip(C, R):
+            keep &= ((p - c) ** 2).sum(1) > r * r
+        p = p[keep]
+        out.append(p)
+        have += len(p)
+    X = np.concatenate(out)[:n_points]
+    return np.ascontiguousarray(X, dtype=np.float32), C, R
