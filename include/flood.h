@@ -51,7 +51,7 @@ typedef int32_t flood_status;
 const char *flood_last_error(void);
 
 /* ---------------------------------------------------------------------------
- * Farthest-point landmarks (Sec. 2 "Theoretical results": greedy k-centre,
+ * Farthest-point landmarks (Sec. 3.2: greedy k-centre,
  * a 2-approximation of the optimal covering radius; the paper's pipeline
  * selects landmarks this way, Sec. 5 and Table 1 "Landmark select.").
  *
@@ -162,9 +162,12 @@ void flood_diagram_free(flood_diagram *dg);
  * (the vertex order fixes the meaning of win_a).  The 0-simplices are the
  * landmarks themselves, in order.
  *
- * landmarks_in_x = 1 asserts that landmark row j is the point
- * X[l_xidx[j]] bit for bit (true for FPS landmarks); it enables the per-
- * sample bound d(p, X) <= min_i ||p - v_i|| from the proof of Lemma 7.
+ * landmarks_in_x = 1 supplies l_xidx, the global X row of each landmark
+ * (for FPS landmarks, Lxyz[j] = X[l_xidx[j]]); it enables the per-sample
+ * bound d(p, X) <= min_i ||p - X[l_xidx[v_i]]|| from the proof of Lemma 7,
+ * which speeds the search and never changes a value.  The bound is taken
+ * from X itself, so it holds even when Lxyz no longer equals those rows; a
+ * row outside the landmark's own cloud contributes no bound.
  */
 typedef struct {
     int32_t B;               /* number of clouds, >= 1 */
@@ -198,7 +201,8 @@ typedef struct {
  * tile_events: optional caller-created hipEvent_t handles; entries 3d,
  * 3d+1 and 3d+2 are recorded on `stream` before the cooperative tile search
  * of dimension d, between it and the per-sample search, and after the
- * per-sample search (NULL entries are skipped).  For profiling only.
+ * per-sample search (NULL entries are skipped).  grid_events: the same, recorded
+ * before and after the grid build.  For profiling only.
  * stats: device uint64 [16] or NULL; receives (+=), for dimension d,
  * [4d+1] samples handed to the per-sample search, [4d+2] evaluations in the
  * cooperative tile search, [4d+3] evaluations in the per-sample search. */
@@ -209,6 +213,7 @@ typedef struct {
     uint64_t *evals;
     void *tile_events[12];
     uint64_t *stats;
+    void *grid_events[2];
 } flood_outputs;
 
 /* Tuning knobs; pass NULL for the defaults (a zero field also selects its
@@ -219,13 +224,17 @@ typedef struct {
  * per-sample search, 1..32, default 6; -1 sends every sample to the
  * per-sample search),
  * tile_extent (a tile whose samples span more cells than this along an axis
- * skips the cooperative search, 2..64, default 24). */
+ * skips the cooperative search, 2..64, default 24),
+ * queue_grab (open samples a wave of the per-sample search takes from the
+ * queue per atomic: 1, 2, 4 or 8; default 4 when a dimension hands more
+ * than 2^19 samples to that search, else 2). */
 typedef struct {
     float cells_per_point;
     int32_t samples_per_lane;
     int32_t waves_per_block;
     int32_t tile_shells;
     int32_t tile_extent;
+    int32_t queue_grab;
 } flood_tuning;
 
 size_t flood_filtration_workspace_size(const flood_problem *pb, const flood_tuning *tune);

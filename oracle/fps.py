@@ -1,6 +1,6 @@
 """Farthest-point landmark selection (oracle; test infrastructure).
 
-Greedy k-centre (Sec. 2, "Theoretical results": FPS is a 2-approximation
+Greedy k-centre (Sec. 3.2, "Theoretical results": FPS is a 2-approximation
 of the optimal covering radius).  The arithmetic recipe is fixed in
 float32 so that a GPU implementation can match the indices bit for bit:
 dx = x - l rounded to float32 per axis; d2 = (dx*dx + dy*dy) + dz*dz with

@@ -27,12 +27,12 @@ class Problem(ctypes.Structure):
 
 class Outputs(ctypes.Structure):
     _fields_ = [("f", c_vp * 4), ("win_x", c_vp * 4), ("win_a", c_vp * 4), ("evals", c_vp),
-                ("tile_events", c_vp * 12), ("stats", c_vp)]
+                ("tile_events", c_vp * 12), ("stats", c_vp), ("grid_events", c_vp * 2)]
 
 
 class Tuning(ctypes.Structure):
     _fields_ = [("cells_per_point", c_f32), ("samples_per_lane", c_i32), ("waves_per_block", c_i32),
-                ("tile_shells", c_i32), ("tile_extent", c_i32)]
+                ("tile_shells", c_i32), ("tile_extent", c_i32), ("queue_grab", c_i32)]
 
 
 _lib = None

@@ -39,9 +39,14 @@ def _check_points(X, name):
 # landmarks
 
 
-def fps_batched(X: torch.Tensor, x_off, n_lm, start=None):
+def fps_batched(X: torch.Tensor, x_off, n_lm, start=None, check_indices: bool = True):
     """Farthest-point landmarks for B clouds concatenated in X ([sum N, 3]).
-    Returns (idx int32 [sum n_lm] local to each cloud, radius float32)."""
+    Returns (idx int32 [sum n_lm] local to each cloud, radius float32).
+
+    A cooperative launch that stops hearing from its workgroups leaves -1 for
+    the landmarks it did not decide; with check_indices (the default) the call
+    synchronises and raises FloodError(EHIP) in that case.  Callers that time
+    repeated calls pass False and check the indices themselves."""
     _check_points(X, "X")
     dev = X.device
     x_off_h, x_off_p = _i64_host(x_off)
@@ -61,12 +66,23 @@ def fps_batched(X: torch.Tensor, x_off, n_lm, start=None):
     ws = torch.empty(max(ws_n, 1), dtype=torch.uint8, device=dev)
     check(L.flood_fps(_ptr(X), B, x_off_p, _ptr(x_off_d), n_lm_p, _ptr(n_lm_d), _ptr(start_d), _ptr(idx),
                       _ptr(radius), _ptr(ws), ws_n, _stream()))
+    if check_indices:
+        check_landmarks(idx)
     return idx, radius
 
 
-def fps(X: torch.Tensor, n_landmarks: int, start: int = 0):
+def check_landmarks(idx: torch.Tensor):
+    """Raises FloodError(EHIP) if any landmark index is negative (an exchange
+    of the cooperative FPS launch was given up)."""
+    if idx.numel() and int(idx.min()) < 0:
+        bad = int((idx < 0).sum())
+        raise _lib.FloodError(_lib.EHIP, "flood_fps: %d landmark(s) left undecided (cooperative exchange "
+                                         "gave up)" % bad)
+
+
+def fps(X: torch.Tensor, n_landmarks: int, start: int = 0, check_indices: bool = True):
     """Farthest-point landmarks of one cloud: (idx int32 [L], radius float32 [L])."""
-    return fps_batched(X, [0, X.shape[0]], [n_landmarks], [start])
+    return fps_batched(X, [0, X.shape[0]], [n_landmarks], [start], check_indices)
 
 
 # ---------------------------------------------------------------------------
@@ -254,6 +270,7 @@ def _tuning(tuning):
     t.waves_per_block = int(tuning.get("waves_per_block", 0))
     t.tile_shells = int(tuning.get("tile_shells", 0))
     t.tile_extent = int(tuning.get("tile_extent", 0))
+    t.queue_grab = int(tuning.get("queue_grab", 0))
     return t
 
 

@@ -43,12 +43,14 @@ flood_tuning default_tuning(const flood_tuning *t) {
     r.waves_per_block = 4;
     r.tile_shells = 6;
     r.tile_extent = 24;
+    r.queue_grab = 0;
     if (t) {
         if (t->cells_per_point != 0) r.cells_per_point = t->cells_per_point;
         if (t->samples_per_lane != 0) r.samples_per_lane = t->samples_per_lane;
         if (t->waves_per_block != 0) r.waves_per_block = t->waves_per_block;
         if (t->tile_shells != 0) r.tile_shells = t->tile_shells;
         if (t->tile_extent != 0) r.tile_extent = t->tile_extent;
+        r.queue_grab = t->queue_grab;
     }
     return r;
 }
@@ -62,6 +64,8 @@ flood_status check_tuning(const flood_tuning &t) {
     if (t.tile_shells < -1 || t.tile_shells > 32 || t.tile_shells == 0)
         return fail(FLOOD_EINVAL, "tuning: tile_shells must be -1 or in [1, 32]");
     if (t.tile_extent < 2 || t.tile_extent > 64) return fail(FLOOD_EINVAL, "tuning: tile_extent outside [2, 64]");
+    if (t.queue_grab != 0 && t.queue_grab != 1 && t.queue_grab != 2 && t.queue_grab != 4 && t.queue_grab != 8)
+        return fail(FLOOD_EINVAL, "tuning: queue_grab must be 0, 1, 2, 4 or 8");
     return FLOOD_OK;
 }
 

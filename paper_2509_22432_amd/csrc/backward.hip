@@ -7,7 +7,7 @@
 
 namespace flood {
 
-__global__ void k_backward(int d, int k, int64_t n, const float *__restrict__ X, const float *__restrict__ L,
+__global__ void k_backward(int d, int k, int64_t n, int64_t n_pts, const float *__restrict__ X, const float *__restrict__ L,
                            const int32_t *__restrict__ simp, const float *__restrict__ gf,
                            const int32_t *__restrict__ win_x, const uint32_t *__restrict__ win_a,
                            float *__restrict__ gX, float *__restrict__ gL) {
@@ -22,6 +22,7 @@ __global__ void k_backward(int d, int k, int64_t n, const float *__restrict__ X,
     float sx, sy, sz;
     sample_point(L, v, a, d, k, sx, sy, sz);
     const int64_t xi = win_x[j];
+    if (xi < 0 || xi >= n_pts) return;  // no winner point recorded: no gradient
     const float dx = sx - X[3 * xi], dy = sy - X[3 * xi + 1], dz = sz - X[3 * xi + 2];
     const float nrm = sqrtf(dx * dx + dy * dy + dz * dz);
     if (!(nrm > 0.f)) return;
@@ -48,7 +49,7 @@ hipError_t backward_run(const flood_problem *pb, const flood_outputs *fwd, const
     for (int d = 0; d < 4; ++d) {
         const int64_t n = d == 0 ? pb->l_off[pb->B] : pb->s_off[d][pb->B];
         if (n == 0 || grad_f[d] == nullptr) continue;
-        hipLaunchKernelGGL(k_backward, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, d, pb->k, n, pb->X,
+        hipLaunchKernelGGL(k_backward, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, d, pb->k, n, pb->x_off[pb->B], pb->X,
                            pb->Lxyz, d == 0 ? nullptr : pb->simp[d], grad_f[d], fwd->win_x[d], fwd->win_a[d],
                            grad_X, grad_L);
     }

@@ -163,7 +163,8 @@ __device__ __forceinline__ void publish(uint64_t *key, const float *seed, int32_
 
 template <int T>
 __global__ __launch_bounds__(kWaveBlock) __attribute__((amdgpu_waves_per_eu(T == 1 ? 8 : 1, 8))) void k_flood_tiles(
-    TileArgs a, const float *__restrict__ L, const int32_t *__restrict__ simp, const int64_t *__restrict__ s_off,
+    TileArgs a, const float *__restrict__ L, const float *__restrict__ X, const int32_t *__restrict__ l_xidx,
+    const int64_t *__restrict__ x_off, const int32_t *__restrict__ simp, const int64_t *__restrict__ s_off,
     const int64_t *__restrict__ tile_off, const float *__restrict__ seed, uint64_t *__restrict__ key,
     const GridParam *__restrict__ gp, const uint32_t *__restrict__ cs, const float4 *__restrict__ xs,
     const uint32_t *__restrict__ order, OpenSample *__restrict__ hard, uint32_t *__restrict__ hard_count,
@@ -189,6 +190,7 @@ __global__ __launch_bounds__(kWaveBlock) __attribute__((amdgpu_waves_per_eu(T ==
     const GridParam g = gp[b];
     const int64_t sbase = s_off[b];
     const int64_t S = (s_off[b + 1] - sbase) * (int64_t)a.n_int;
+    const int64_t x_lo = x_off[b], x_hi = x_off[b + 1];
     const int64_t ls0 = (wave - tile_off[b]) * 64 * T;
     const int d = a.d;
 
@@ -218,8 +220,14 @@ __global__ __launch_bounds__(kWaveBlock) __attribute__((amdgpu_waves_per_eu(T ==
             sample_point(L, v, comp, d, a.k, sx[t], sy[t], sz[t]);
             float u = INFINITY;
             if (a.landmarks_in_x) {
-                for (int i = 0; i <= d; ++i)
-                    u = fminf(u, dist2(sx[t], sy[t], sz[t], L[3 * v[i]], L[3 * v[i] + 1], L[3 * v[i] + 2]));
+                // the bound is the distance to the landmark's own point of X
+                // (read from X, so it holds whatever the landmark array holds;
+                // a row outside the cloud gives no bound)
+                for (int i = 0; i <= d; ++i) {
+                    const int64_t xi = l_xidx[v[i]];
+                    if (xi >= x_lo && xi < x_hi)
+                        u = fminf(u, dist2(sx[t], sy[t], sz[t], X[3 * xi], X[3 * xi + 1], X[3 * xi + 2]));
+                }
             }
             best[t] = u;
             M[t] = seed[j];
@@ -518,6 +526,7 @@ __global__ __launch_bounds__(kWaveBlock) __attribute__((amdgpu_waves_per_eu(T ==
 
 struct DeepArgs {
     int32_t d, k, n_int, B;
+    uint32_t grab;  // queue entries per atomic; 0: kGrab above 2^19 open samples, else kGrabSmall
 };
 
 __device__ __forceinline__ void ring_pos(int i, int &r, int &dy, int &dz) {
@@ -656,7 +665,7 @@ __device__ __forceinline__ int find_cloud(const int64_t *__restrict__ s_off, int
     return lo_b;
 }
 
-static constexpr uint32_t kGrab = 4;    // queue entries a wave takes per atomic, at most
+static constexpr uint32_t kGrab = 4;    // queue entries a wave takes per atomic on long queues
 static constexpr uint32_t kGrabSmall = 2;  // for short queues (tail balance); long queues take kGrab (fewer atomics)
 static constexpr uint32_t kSeg = 2048;  // queue segment of one XCD (spatially adjacent open samples)
 
@@ -681,7 +690,7 @@ __global__ __launch_bounds__(kWaveBlock) __attribute__((amdgpu_waves_per_eu(8, 8
     // queue segments x, x+8, ... through its own counter, so neighbouring
     // samples (same tile, same grid rows) meet in one L2
     const uint32_t xcd = blockIdx.x & 7u;
-    const uint32_t grab = n > (1u << 19) ? kGrab : kGrabSmall;
+    const uint32_t grab = a.grab ? a.grab : (n > (1u << 19) ? kGrab : kGrabSmall);
     while (true) {
         uint32_t v0 = 0;
         if (lane == 0) v0 = atomicAdd(&queue_next[xcd], grab);
@@ -847,12 +856,13 @@ size_t flood_workspace(const flood_problem *pb, float alpha, FloodSizes *sz) {
 }
 
 template <int T>
-static void launch_tiles(const TileArgs &ta, int wpb, hipStream_t s, const float *L, const int32_t *simp,
+static void launch_tiles(const TileArgs &ta, int wpb, hipStream_t s, const flood_problem *pb, const int32_t *simp,
                          const int64_t *s_off, const int64_t *tile_off, const float *seed, uint64_t *key,
                          const GridWork &g, const uint32_t *order, OpenSample *hard, uint32_t *hard_count,
                          uint64_t *evals, uint64_t *stats) {
     const int64_t nb = (ta.n_tiles + wpb - 1) / wpb;
-    hipLaunchKernelGGL(k_flood_tiles<T>, dim3((unsigned)nb), dim3(64 * wpb), 0, s, ta, L, simp, s_off, tile_off,
+    hipLaunchKernelGGL(k_flood_tiles<T>, dim3((unsigned)nb), dim3(64 * wpb), 0, s, ta, pb->Lxyz, pb->X, pb->l_xidx,
+                       pb->x_off_d, simp, s_off, tile_off,
                        seed, key, g.gp, g.cell_start, g.xs, order, hard, hard_count, (unsigned long long *)evals,
                        (unsigned long long *)stats);
 }
@@ -893,8 +903,11 @@ hipError_t flood_run(const flood_problem *pb, const flood_tuning &tu, const floo
     for (int d = 0; d < 4; ++d) tile_off[d] = c.take<int64_t>(pb->B + 1);
     if (!c.ok()) return hipErrorOutOfMemory;
 
-    hipError_t e = grid_build(pb->X, pb->B, pb->x_off, pb->x_off_d, tu.cells_per_point, g, s);
+    hipError_t e = hipSuccess;
+    if (out->grid_events[0] && (e = hipEventRecord((hipEvent_t)out->grid_events[0], s)) != hipSuccess) return e;
+    e = grid_build(pb->X, pb->B, pb->x_off, pb->x_off_d, tu.cells_per_point, g, s);
     if (e != hipSuccess) return e;
+    if (out->grid_events[1] && (e = hipEventRecord((hipEvent_t)out->grid_events[1], s)) != hipSuccess) return e;
     const int T = tu.samples_per_lane;
     const int wpb = tu.waves_per_block;
     for (int d = 0; d < 4; ++d) {
@@ -945,9 +958,9 @@ hipError_t flood_run(const flood_problem *pb, const flood_tuning &tu, const floo
                     e = hipEventRecord((hipEvent_t)out->tile_events[3 * d], s);
                     if (e != hipSuccess) return e;
                 }
-                if (T == 1) launch_tiles<1>(ta, wpb, s, pb->Lxyz, simp, soff_d, tile_off[d], seed, key, g, order, hard, counters, out->evals, out->stats);
-                else if (T == 2) launch_tiles<2>(ta, wpb, s, pb->Lxyz, simp, soff_d, tile_off[d], seed, key, g, order, hard, counters, out->evals, out->stats);
-                else launch_tiles<4>(ta, wpb, s, pb->Lxyz, simp, soff_d, tile_off[d], seed, key, g, order, hard, counters, out->evals, out->stats);
+                if (T == 1) launch_tiles<1>(ta, wpb, s, pb, simp, soff_d, tile_off[d], seed, key, g, order, hard, counters, out->evals, out->stats);
+                else if (T == 2) launch_tiles<2>(ta, wpb, s, pb, simp, soff_d, tile_off[d], seed, key, g, order, hard, counters, out->evals, out->stats);
+                else launch_tiles<4>(ta, wpb, s, pb, simp, soff_d, tile_off[d], seed, key, g, order, hard, counters, out->evals, out->stats);
                 if (out->tile_events[3 * d + 1]) {
                     e = hipEventRecord((hipEvent_t)out->tile_events[3 * d + 1], s);
                     if (e != hipSuccess) return e;
@@ -957,6 +970,7 @@ hipError_t flood_run(const flood_problem *pb, const flood_tuning &tu, const floo
                 da.k = pb->k;
                 da.n_int = (int32_t)nint;
                 da.B = pb->B;
+                da.grab = (uint32_t)tu.queue_grab;
                 hipLaunchKernelGGL(k_flood_deep, dim3(2048), dim3(256), 0, s, da, seed, key,
                                    g.gp, g.cell_start, g.occ, g.xs, hard, counters, counters + 8,
                                    (unsigned long long *)out->evals, (unsigned long long *)out->stats);

@@ -69,3 +69,45 @@ def test_autograd_function_routes_gradients():
     res["run"].backward([torch.full_like(res["run"].f[d], d + 1.0) for d in range(4)], gX, gL)
     torch.cuda.synchronize()
     assert torch.allclose(Xg.grad, gX, atol=1e-5) and torch.allclose(Lg.grad, gL, atol=1e-5)
+
+
+def test_batched_backward_matches_oracle_gradient():
+    # four clouds in one batched forward + backward; every dimension carries
+    # nonzero weights (vertices included: f = 0 there, so u = 0 on both
+    # sides), near ties excluded as above
+    import paper_2509_22432_amd as P
+    from paper_2509_22432_amd import batch
+    clouds = synth.differentiable_clouds(4, 2500, seed=77)
+    k = 6
+    pb, Ls, cxs = batch.prepare(clouds, [40, 48, 56, 40], k)
+    run = P.filtration(pb)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(8)
+    w_all = {d: np.zeros(pb.n(d)) for d in range(4)}
+    gX_ref, gL_ref = [], []
+    for b, X in enumerate(clouds):
+        cx = oracle_complex(cxs[b])
+        Lx = Ls[b]
+        diam = OF.diameter(X)
+        vals = OF.flood_all(X, Lx, cx, k, "brute")
+        w = {}
+        for d in range(4):
+            w[d] = rng.random(len(vals[d][0]))
+            if d > 0:
+                simp = cx[{1: "E", 2: "F", 3: "T"}[d]]
+                w[d][_tie_gap(X, Lx, simp, d, k) <= 1e-4 * diam] = 0.0
+            off = int(pb.l_off[b]) if d == 0 else int(pb.s_off[d][b])
+            w_all[d][off:off + len(w[d])] = w[d]
+        gx, gl = OF.gradient(X, Lx, cx, vals, k, w)
+        gX_ref.append(gx)
+        gL_ref.append(gl)
+    gX_ref, gL_ref = np.concatenate(gX_ref), np.concatenate(gL_ref)
+    gX = torch.zeros_like(pb.X)
+    gL = torch.zeros_like(pb.Lxyz)
+    run.backward([torch.from_numpy(w_all[d].astype(np.float32)).to(gX.device) for d in range(4)], gX, gL)
+    torch.cuda.synchronize()
+    gX, gL = gX.cpu().numpy(), gL.cpu().numpy()
+    print("batched: max |dgX|", np.abs(gX - gX_ref).max(), "max |dgL|", np.abs(gL - gL_ref).max(),
+          "weighted simplices", [int((w_all[d] > 0).sum()) for d in range(4)])
+    assert np.abs(gX - gX_ref).max() <= 1e-4 * (1 + np.abs(gX_ref).max())
+    assert np.abs(gL - gL_ref).max() <= 1e-4 * (1 + np.abs(gL_ref).max())

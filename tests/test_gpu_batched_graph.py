@@ -1,0 +1,112 @@
+"""The batched form exactly as the benchmark times it: 512 clouds of uneven
+size (N log-uniform in [1e4, 5e5], 1-6 noisy primitives, L = min(N/100,
+4096), k = 6), the whole filtration captured once in a HIP graph and
+replayed.
+
+* Every replay equals the eager call bit for bit (values, winners), with
+  eager work and synchronisations between the replays.
+* The per-sample search of some dimension receives more than 2^19 open
+  samples, so the replays take the long-queue branch (four queue entries per
+  atomic); every explicit queue grab gives the same bits.
+* The batched result equals one plain call per cloud.
+* Sampled simplices of every cloud agree with the FP64 oracle (masked mode)
+  within 1e-5 * diam of that cloud; the largest |df| / diam per dimension is
+  printed.
+"""
+import numpy as np
+import pytest
+import torch
+
+import paper_2509_22432_amd as P
+import synth
+from oracle import flood as OF
+from paper_2509_22432_amd import api, batch
+
+pytestmark = pytest.mark.gpu
+SIMP = {1: "E", 2: "F", 3: "T"}
+K = 6
+
+
+def _snap(run):
+    return ([t.cpu().numpy().copy() for t in run.f], [t.cpu().numpy().copy() for t in run.win_x],
+            [t.cpu().numpy().copy() for t in run.win_a])
+
+
+def _same(a, b, what):
+    for part, name in zip(range(3), ("f", "win_x", "win_a")):
+        for d in range(4):
+            assert np.array_equal(a[part][d], b[part][d]), (what, name, d)
+
+
+@pytest.fixture(scope="module")
+def b512():
+    clouds, lms = synth.batched_clouds(512)
+    print("batch512: %d clouds, %d points" % (len(clouds), sum(map(len, clouds))), flush=True)
+    pb, Ls, cxs = batch.prepare(clouds, lms, K)
+    gf = batch.GraphedFiltration(pb)
+    gf.run.stats.zero_()
+    gf.replay()
+    torch.cuda.synchronize()
+    r1 = _snap(gf.run)
+    open_samples = gf.run.stats.view(4, 4)[:, 1].cpu().numpy().copy()
+    eager = P.filtration(pb)
+    torch.cuda.synchronize()
+    ref = _snap(eager)
+    gf.replay()
+    torch.cuda.synchronize()
+    r2 = _snap(gf.run)
+    print("batch512: open samples per dimension", open_samples.tolist(), flush=True)
+    return dict(clouds=clouds, lms=lms, pb=pb, Ls=Ls, cxs=cxs, r1=r1, r2=r2, ref=ref, open=open_samples)
+
+
+def test_graph_replays_equal_eager(b512):
+    _same(b512["r1"], b512["ref"], "replay 1")
+    _same(b512["r2"], b512["ref"], "replay 2")
+
+
+def test_long_queue_branch_taken_and_grab_invariant(b512):
+    assert b512["open"].max() > (1 << 19)
+    for grab in (1, 2, 8):
+        run = P.filtration(b512["pb"], {"queue_grab": grab}, count_evals=False)
+        torch.cuda.synchronize()
+        _same(_snap(run), b512["ref"], "queue_grab %d" % grab)
+        del run
+
+
+def test_batched_equals_plain_per_cloud(b512):
+    pb, ref = b512["pb"], b512["ref"]
+    for b, c in enumerate(b512["clouds"]):
+        Xb = torch.from_numpy(c).cuda()
+        Lb = torch.from_numpy(b512["Ls"][b]).cuda()
+        li = (pb.l_xidx[int(pb.l_off[b]):int(pb.l_off[b + 1])] - int(pb.x_off[b])).contiguous()
+        p1 = api.problem_from_complexes(Xb, [0, len(c)], Lb, [0, len(b512["Ls"][b])], [b512["cxs"][b]], K,
+                                        l_xidx=li)
+        one = _snap(P.filtration(p1, count_evals=False))
+        for d in range(4):
+            so = pb.l_off if d == 0 else pb.s_off[d]
+            sl = slice(int(so[b]), int(so[b + 1]))
+            assert np.array_equal(one[0][d], ref[0][d][sl]), (b, d)
+            assert np.array_equal(one[1][d], ref[1][d][sl] - int(pb.x_off[b])), (b, d)
+            assert np.array_equal(one[2][d], ref[2][d][sl]), (b, d)
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("part", range(4))
+def test_sampled_against_oracle(b512, part):
+    pb, f = b512["pb"], b512["ref"][0]
+    rng = np.random.default_rng(500 + part)
+    worst = np.zeros(4)
+    for b in range(part * 128, (part + 1) * 128):
+        X = b512["clouds"][b]
+        cx = b512["cxs"][b]
+        diam = OF.diameter(X)
+        xs = OF.XSorted(X)
+        for d in range(4):
+            simp = np.arange(cx.L).reshape(-1, 1) if d == 0 else getattr(cx, SIMP[d])
+            off = int(pb.l_off[b]) if d == 0 else int(pb.s_off[d][b])
+            pick = rng.choice(len(simp), min(10 if d == 0 else 40, len(simp)), replace=False)
+            ref, _, _ = OF.flood_dim(X, b512["Ls"][b], simp[pick], d, K, "masked", xs)
+            err = np.abs(f[d][off + pick].astype(np.float64) - ref).max() / diam
+            worst[d] = max(worst[d], err)
+            assert err <= 1e-5, (b, d, err)
+    print("clouds %d-%d: max|df|/diam per dimension %s" % (part * 128, part * 128 + 127, worst.tolist()), flush=True)

@@ -211,3 +211,45 @@ def test_config2_sampled_against_masked_oracle():
         err = np.abs(res["out"]["f"][d][pick].astype(np.float64) - ref).max()
         print("dim", d, "max|df| on 150 sampled", err)
         assert err <= 1e-5 * diam
+
+
+def test_base_tuning_against_oracle_and_metamorphic():
+    # the default-tuning run the invariance test compares against, checked
+    # against the masked oracle; then two transformations that must leave
+    # the values exactly as they are: a permutation of the rows of X (the
+    # landmarks kept as the same points), and scaling every coordinate by 2
+    # (every correctly rounded operation commutes with it, so f doubles bit
+    # for bit and the landmark indices do not change)
+    X = synth.config_cloud(2, 100_000)
+    k = 6
+    base = run_single(X, 400, k)
+    xs = OF.XSorted(X)
+    diam = OF.diameter(X)
+    rng = np.random.default_rng(21)
+    for d in (1, 2, 3):
+        simp = getattr(base["cx"], SIMP[d])
+        pick = rng.choice(len(simp), 300, replace=False)
+        ref, _, _ = OF.flood_dim(X, base["Lxyz"], simp[pick], d, k, "masked", xs)
+        assert np.abs(base["out"]["f"][d][pick].astype(np.float64) - ref).max() <= 1e-5 * diam
+    perm = rng.permutation(len(X))
+    inv = np.empty_like(perm)
+    inv[perm] = np.arange(len(X))
+    Xp = np.ascontiguousarray(X[perm])
+    Xd = torch.from_numpy(Xp).to(dev())
+    lx = torch.from_numpy(inv[base["idx"]].astype(np.int32)).to(dev())
+    Ld = torch.from_numpy(base["Lxyz"]).to(dev())
+    pb = P.problem_from_complexes(Xd, [0, len(X)], Ld, [0, len(base["Lxyz"])], [base["cx"]], k, l_xidx=lx)
+    run = P.filtration(pb)
+    torch.cuda.synchronize()
+    for d in range(4):
+        assert np.array_equal(run.f[d].cpu().numpy(), base["out"]["f"][d]), d
+        assert np.array_equal(run.win_a[d].cpu().numpy().view(np.uint32), base["out"]["win_a"][d]), d
+        # x* is the same point (exact ties between distinct points, where the
+        # lowest row would decide, do not occur in these noisy clouds)
+        assert np.array_equal(Xp[run.win_x[d].cpu().numpy()], X[base["out"]["win_x"][d]]), d
+    scaled = run_single(np.ascontiguousarray(X * np.float32(2)), 400, k)
+    assert np.array_equal(scaled["idx"], base["idx"])
+    for d in range(4):
+        assert np.array_equal(scaled["out"]["f"][d], np.float32(2) * base["out"]["f"][d]), d
+        assert np.array_equal(scaled["out"]["win_a"][d], base["out"]["win_a"][d]), d
+        assert np.array_equal(scaled["out"]["win_x"][d], base["out"]["win_x"][d]), d

@@ -79,7 +79,7 @@ def test_gradient_at_differentiable_shape():
     diam = OF.diameter(X)
     xs = OF.XSorted(X)
     rng = np.random.default_rng(4)
-    w = {0: np.zeros(512)}
+    w = {0: rng.random(512)}  # f = 0 on vertices: u = 0 on both sides
     vals = {0: OF.flood_dim(X, Lx, np.arange(512).reshape(-1, 1), 0, k, "masked", xs)}
     for d in (1, 2, 3):
         simp = cxo[SIMP[d]]
@@ -104,5 +104,5 @@ def test_gradient_at_differentiable_shape():
     torch.cuda.synchronize()
     gX, gL = gX.cpu().numpy(), gL.cpu().numpy()
     print("max |dgX|", np.abs(gX - gX_ref).max(), "max |dgL|", np.abs(gL - gL_ref).max())
-    assert np.abs(gX - gX_ref).max() <= 1e-3 * (1 + np.abs(gX_ref).max())
-    assert np.abs(gL - gL_ref).max() <= 1e-3 * (1 + np.abs(gL_ref).max())
+    assert np.abs(gX - gX_ref).max() <= 1e-4 * (1 + np.abs(gX_ref).max())
+    assert np.abs(gL - gL_ref).max() <= 1e-4 * (1 + np.abs(gL_ref).max())

@@ -65,7 +65,8 @@ def test_filtration_rejects_small_workspace_and_bad_tuning():
     # the tile kernel runs at most four waves per block
     t = _lib.Tuning(1.0, 1, 5, 0, 0)
     assert L.flood_filtration(ctypes.byref(pb), ctypes.byref(t), ctypes.byref(out), None, 0, None) == _lib.EINVAL
-    for bad in ((1.0, 1, 4, 33, 0), (1.0, 1, 4, -2, 0), (1.0, 1, 4, 0, 65), (1.0, 1, 4, 0, 1)):
+    for bad in ((1.0, 1, 4, 33, 0), (1.0, 1, 4, -2, 0), (1.0, 1, 4, 0, 65), (1.0, 1, 4, 0, 1), (1.0, 1, 4, 0, 0, 3),
+                (1.0, 1, 4, 0, 0, 16), (1.0, 1, 4, 0, 0, -1)):
         t = _lib.Tuning(*bad)
         assert L.flood_filtration(ctypes.byref(pb), ctypes.byref(t), ctypes.byref(out), None, 0, None) == _lib.EINVAL
 
@@ -131,3 +132,14 @@ def test_delaunay_errors():
     with pytest.raises(P.FloodError) as e:
         P.delaunay(bad)
     assert e.value.status == _lib.EINVAL
+
+
+def test_fps_undecided_landmarks_raise():
+    # a cooperative FPS launch that gives up an exchange leaves -1 indices;
+    # the binding turns them into an error instead of indexing row -1
+    import torch
+    from paper_2509_22432_amd import api
+    api.check_landmarks(torch.tensor([0, 5, 3], dtype=torch.int32))
+    with pytest.raises(P.FloodError) as e:
+        api.check_landmarks(torch.tensor([0, 5, -1, -1], dtype=torch.int32))
+    assert e.value.status == _lib.EHIP and "2 landmark" in str(e.value)
