@@ -78,8 +78,10 @@ const char *flood_last_error(void);
  * EDEGENERATE cannot be detected before the run: if a cloud has fewer
  * distinct points than landmarks, its remaining indices repeat an earlier
  * landmark and its radius reaches 0; callers check radius.
- * Clouds of at least 2^19 points run as one cooperative launch (one
- * workgroup per CU exchanging candidates through the workspace); the call
+ * Clouds of at least 2^19 points (2^14 in calls of at most 8 clouds) run
+ * as one cooperative launch each (one workgroup per CU exchanging candidates
+ * through the workspace); the other clouds share one launch with a
+ * workgroup per cloud.  The call
  * fails with FLOOD_EHIP if the device cannot co-schedule it.  Should the
  * workgroups stop hearing from each other (a poll limit of about 4M polls
  * per exchange), the launch ends and the cloud's undecided indices are -1:
@@ -162,6 +164,21 @@ void flood_diagram_free(flood_diagram *dg);
  * (the vertex order fixes the meaning of win_a).  The 0-simplices are the
  * landmarks themselves, in order.
  *
+ * sampling selects the sample sets P_sigma:
+ *  - FLOOD_SAMPLING_GRID (0): the barycentric grid of Lemma 6 with k
+ *    segments per edge, k <= 255 (equation (1) above);
+ *  - FLOOD_SAMPLING_RANDOM (1): every simplex of dimension >= 1 owns k
+ *    points drawn uniformly from its convex hull (Thm. 5 holds for any
+ *    finite P_sigma inside conv sigma; Lemma 9 bounds the covering radius of
+ *    uniform draws), 1 <= k <= 65536, and f(sigma) = max(own value, max
+ *    over facets f(tau)) -- the face sets are not subsets of the coface's
+ *    here, so this closure of Sec. 4.1 is what makes f monotone.  Sample q
+ *    of the simplex in cloud-local row r of dimension d is
+ *    sum_i w_i v_i, the weights being the spacings of the sorted uniforms
+ *    u_i = (word_i >> 40) * 2^-24, i < d, of Philox4x64-10 (Salmon et al.,
+ *    SC 2011) at counter (q, r, d, 0) and key (seed, 0): u_(1),
+ *    u_(2) - u_(1), ..., 1 - u_(d).  A vertex owns itself.
+ *
  * landmarks_in_x = 1 supplies l_xidx, the global X row of each landmark
  * (for FPS landmarks, Lxyz[j] = X[l_xidx[j]]); it enables the per-sample
  * bound d(p, X) <= min_i ||p - X[l_xidx[v_i]]|| from the proof of Lemma 7,
@@ -169,11 +186,14 @@ void flood_diagram_free(flood_diagram *dg);
  * from X itself, so it holds even when Lxyz no longer equals those rows; a
  * row outside the landmark's own cloud contributes no bound.
  */
+#define FLOOD_SAMPLING_GRID 0
+#define FLOOD_SAMPLING_RANDOM 1
 typedef struct {
     int32_t B;               /* number of clouds, >= 1 */
-    int32_t k;               /* segments per edge, 1..255 (k+1 samples per edge) */
+    int32_t k;               /* grid: segments per edge, 1..255 (k+1 samples per edge);
+                                random: samples per simplex, 1..65536 */
     int32_t landmarks_in_x;  /* 0 or 1 (see above) */
-    int32_t reserved;
+    int32_t sampling;        /* FLOOD_SAMPLING_GRID or FLOOD_SAMPLING_RANDOM */
     const float *X;          /* device [sum N][3] */
     const int64_t *x_off;    /* host [B+1] */
     const int64_t *x_off_d;  /* device [B+1] */
@@ -186,16 +206,25 @@ typedef struct {
     const int64_t *s_off_d[4]; /* device [B+1] per dimension (s_off_d[0] unused) */
     const int32_t *tri_edges; /* device [F][3] */
     const int32_t *tet_tris;  /* device [T][4] */
+    uint64_t seed;            /* random sample sets: the generator's key */
 } flood_problem;
 
 /* Outputs, all device.  f[d] float [n_d]: the flood value (1).  win_x[d]
  * int32 [n_d]: global X row of the nearest point x* of the winning sample
- * s* (lowest row among equidistant points).  win_a[d] uint32 [n_d]: the
- * winning sample's composition a over the simplex's own vertices, a_i in
- * bits 8i..8i+7 (s* = sum_i (a_i/k) v_i; a face-inherited winner carries
- * zeros for the vertices it does not use; the interior sample with the
- * lowest rank in lexicographically descending composition order wins exact
- * ties, and the first attaining facet when the value comes from a face).
+ * s* (lowest row among equidistant points).  win_a[d] uint32 [n_d], grid
+ * sets: the winning sample's composition a over the simplex's own vertices,
+ * a_i in bits 8i..8i+7 (s* = sum_i (a_i/k) v_i; a face-inherited winner
+ * carries zeros for the vertices it does not use; the interior sample with
+ * the lowest rank in lexicographically descending composition order wins
+ * exact ties, and the first attaining facet when the value comes from a
+ * face).  Random sets: q, the winning sample's index within the simplex that
+ * owns it, in bits 0..27, and in bits 28+i whether vertex i of this simplex
+ * is a vertex of that owner (the simplex itself, or the face it inherits
+ * from); the own sample with the lowest q wins ties among own samples, the
+ * own samples win a tie with the facets, else the first attaining facet.
+ * win_w[d] float [n_d][4] or NULL (required by the backward for random
+ * sets): the winning sample's barycentric weights over the simplex's own
+ * vertices, s* = sum_i w_i v_i (zeros for vertices the owner lacks).
  * evals: device uint64 [1] or NULL; receives (+=) the number of sample-point
  * distance evaluations executed for live samples.
  * tile_events: optional caller-created hipEvent_t handles; entries 3d,
@@ -214,6 +243,7 @@ typedef struct {
     void *tile_events[12];
     uint64_t *stats;
     void *grid_events[2];
+    float *win_w[4];
 } flood_outputs;
 
 /* Tuning knobs; pass NULL for the defaults (a zero field also selects its
@@ -243,9 +273,10 @@ flood_status flood_filtration(const flood_problem *pb, const flood_tuning *tune,
 
 /* ---------------------------------------------------------------------------
  * Backward of loss(f) through (1), using the winners of a forward call.
- * Away from ties, f(sigma) = ||s* - x*|| with s* = sum_i (a_i/k) v_i, so
+ * Away from ties, f(sigma) = ||s* - x*|| with s* = sum_i w_i v_i (grid sets:
+ * w_i = a_i/k from win_a; random sets: win_w, which must then be given), so
  * with u = (s* - x*)/||s* - x*|| (u = 0 when f = 0):
- *     grad_X[x*]  -= g u,      grad_L[v_i] += g (a_i / k) u,
+ *     grad_X[x*]  -= g u,      grad_L[v_i] += g w_i u,
  * g = grad_f[d][sigma].  grad_X [sum N][3] and grad_L [sum L][3] (device)
  * are accumulated into (+=); the caller zeroes them.  Uses float atomics,
  * so the summation order (not the terms) varies between runs.

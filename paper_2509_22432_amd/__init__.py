@@ -8,6 +8,6 @@ PyTorch provides device memory and the current HIP stream.
 """
 from .api import (  # noqa: F401
     Complex, FloodFiltration, FloodProblem, delaunay, filtration, fps, fps_batched,
-    n_interior, persistence, problem_from_complexes,
+    n_interior, own_samples, persistence, problem_from_complexes,
 )
 from ._lib import FloodError  # noqa: F401

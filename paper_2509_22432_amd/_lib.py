@@ -9,6 +9,7 @@ c_i32, c_i64, c_f32, c_vp, c_sz = ctypes.c_int32, ctypes.c_int64, ctypes.c_float
 P = ctypes.POINTER
 
 OK, EINVAL, ENOMEM, EHIP, EDEGENERATE, EUNSUPPORTED = 0, 1, 2, 3, 4, 5
+SAMPLING_GRID, SAMPLING_RANDOM = 0, 1
 
 
 class FloodError(RuntimeError):
@@ -18,16 +19,16 @@ class FloodError(RuntimeError):
 
 
 class Problem(ctypes.Structure):
-    _fields_ = [("B", c_i32), ("k", c_i32), ("landmarks_in_x", c_i32), ("reserved", c_i32),
+    _fields_ = [("B", c_i32), ("k", c_i32), ("landmarks_in_x", c_i32), ("sampling", c_i32),
                 ("X", c_vp), ("x_off", P(c_i64)), ("x_off_d", c_vp),
                 ("Lxyz", c_vp), ("l_xidx", c_vp), ("l_off", P(c_i64)), ("l_off_d", c_vp),
                 ("simp", c_vp * 4), ("s_off", P(c_i64) * 4), ("s_off_d", c_vp * 4),
-                ("tri_edges", c_vp), ("tet_tris", c_vp)]
+                ("tri_edges", c_vp), ("tet_tris", c_vp), ("seed", ctypes.c_uint64)]
 
 
 class Outputs(ctypes.Structure):
     _fields_ = [("f", c_vp * 4), ("win_x", c_vp * 4), ("win_a", c_vp * 4), ("evals", c_vp),
-                ("tile_events", c_vp * 12), ("stats", c_vp), ("grid_events", c_vp * 2)]
+                ("tile_events", c_vp * 12), ("stats", c_vp), ("grid_events", c_vp * 2), ("win_w", c_vp * 4)]
 
 
 class Tuning(ctypes.Structure):

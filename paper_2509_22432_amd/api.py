@@ -174,10 +174,20 @@ def n_interior(d: int, k: int) -> int:
     return comb(k - 1, d) if k - 1 >= d else 0
 
 
+def own_samples(d: int, k: int, sampling: str = "grid") -> int:
+    """Samples a d-simplex evaluates itself: its interior grid points, or its
+    k random points (a vertex: itself)."""
+    if d == 0:
+        return 1
+    return k if sampling == "random" else n_interior(d, k)
+
+
 @dataclass
 class FloodProblem:
     """Device-resident description of B clouds and their complexes, reusable
-    across forward / backward / graph replays."""
+    across forward / backward / graph replays.  k: segments per edge of the
+    barycentric grid (sampling "grid") or samples per simplex (sampling
+    "random", drawn with the counter-based generator keyed by `seed`)."""
     B: int
     k: int
     X: torch.Tensor
@@ -190,6 +200,8 @@ class FloodProblem:
     tri_edges: torch.Tensor
     tet_tris: torch.Tensor
     dev_off: dict = field(default_factory=dict)
+    sampling: str = "grid"
+    seed: int = 0
     _struct: Problem | None = None
 
     def n(self, d):
@@ -200,6 +212,8 @@ class FloodProblem:
             return self._struct
         pb = Problem()
         pb.B, pb.k = self.B, self.k
+        pb.sampling = {"grid": _lib.SAMPLING_GRID, "random": _lib.SAMPLING_RANDOM}[self.sampling]
+        pb.seed = int(self.seed) & 0xFFFFFFFFFFFFFFFF
         pb.landmarks_in_x = 1 if self.l_xidx is not None else 0
         pb.X = self.X.data_ptr()
         self._keep = []
@@ -228,9 +242,14 @@ class FloodProblem:
 
 
 def problem_from_complexes(X: torch.Tensor, x_off, Lxyz: torch.Tensor, l_off, complexes, k: int,
-                           l_xidx: torch.Tensor | None = None) -> FloodProblem:
+                           l_xidx: torch.Tensor | None = None, sampling: str = "grid",
+                           seed: int = 0) -> FloodProblem:
     """Concatenate per-cloud complexes (landmark ids local to each cloud) into
-    one device problem with global landmark / edge / triangle rows."""
+    one device problem with global landmark / edge / triangle rows.
+    sampling "grid": k segments per edge (Lemma 6); "random": k points drawn
+    uniformly from every simplex (Lemma 9), keyed by `seed`."""
+    if sampling not in ("grid", "random"):
+        raise ValueError("sampling must be 'grid' or 'random'")
     _check_points(X, "X")
     _check_points(Lxyz, "Lxyz")
     dev = X.device
@@ -258,7 +277,8 @@ def problem_from_complexes(X: torch.Tensor, x_off, Lxyz: torch.Tensor, l_off, co
     for d in (1, 2, 3):
         dev_off[d] = _dev(so[d], torch.int64, dev)
     return FloodProblem(B, k, X, Lxyz, l_xidx, x_off, l_off, so, simp,
-                        _dev(cat(TE, 3), torch.int32, dev), _dev(cat(TT, 4), torch.int32, dev), dev_off)
+                        _dev(cat(TE, 3), torch.int32, dev), _dev(cat(TT, 4), torch.int32, dev), dev_off,
+                        sampling, seed)
 
 
 def _tuning(tuning):
@@ -285,6 +305,7 @@ class FloodRun:
         self.f = [torch.empty(pb.n(d), dtype=torch.float32, device=dev) for d in range(4)]
         self.win_x = [torch.empty(pb.n(d), dtype=torch.int32, device=dev) for d in range(4)]
         self.win_a = [torch.empty(pb.n(d), dtype=torch.int32, device=dev) for d in range(4)]
+        self.win_w = [torch.empty((pb.n(d), 4), dtype=torch.float32, device=dev) for d in range(4)]
         self.evals = torch.zeros(1, dtype=torch.int64, device=dev) if count_evals else None
         self.stats = torch.zeros(16, dtype=torch.int64, device=dev) if count_evals else None
         o = Outputs()
@@ -292,6 +313,7 @@ class FloodRun:
             o.f[d] = self.f[d].data_ptr() if self.f[d].numel() else None
             o.win_x[d] = self.win_x[d].data_ptr() if self.win_x[d].numel() else None
             o.win_a[d] = self.win_a[d].data_ptr() if self.win_a[d].numel() else None
+            o.win_w[d] = self.win_w[d].data_ptr() if self.win_w[d].numel() else None
         o.evals = self.evals.data_ptr() if self.evals is not None else None
         o.stats = self.stats.data_ptr() if self.stats is not None else None
         self.out = o

@@ -16,7 +16,7 @@ import torch
 from . import api
 
 
-def prepare(clouds, n_lm, k, threads=16):
+def prepare(clouds, n_lm, k, threads=16, sampling="grid", seed=0):
     """clouds: list of float32 [N_i, 3] arrays.  Returns (FloodProblem,
     host landmark arrays, complexes)."""
     dev = torch.device("cuda")
@@ -31,7 +31,8 @@ def prepare(clouds, n_lm, k, threads=16):
         cxs = list(ex.map(api.delaunay, Ls))
     gidx = np.concatenate([idx[l_off[b]:l_off[b + 1]] + x_off[b] for b in range(len(clouds))]).astype(np.int32)
     Ld = torch.from_numpy(np.concatenate(Ls)).to(dev)
-    pb = api.problem_from_complexes(Xd, x_off, Ld, l_off, cxs, k, l_xidx=torch.from_numpy(gidx).to(dev))
+    pb = api.problem_from_complexes(Xd, x_off, Ld, l_off, cxs, k, l_xidx=torch.from_numpy(gidx).to(dev),
+                                    sampling=sampling, seed=seed)
     return pb, Ls, cxs
 
 

@@ -73,7 +73,12 @@ flood_status check_problem(const flood_problem *pb) {
     if (!pb) return fail(FLOOD_EINVAL, "problem is NULL");
     if (pb->B < 1) return fail(FLOOD_EINVAL, "problem: B must be >= 1");
     if (pb->k < 1) return fail(FLOOD_EINVAL, "problem: k must be >= 1");
-    if (pb->k > 255) return fail(FLOOD_EUNSUPPORTED, "problem: k > 255 (compositions are packed in 8 bits)");
+    if (pb->sampling != FLOOD_SAMPLING_GRID && pb->sampling != FLOOD_SAMPLING_RANDOM)
+        return fail(FLOOD_EINVAL, "problem: sampling must be FLOOD_SAMPLING_GRID or FLOOD_SAMPLING_RANDOM");
+    if (pb->sampling == FLOOD_SAMPLING_GRID && pb->k > 255)
+        return fail(FLOOD_EUNSUPPORTED, "problem: k > 255 (compositions are packed in 8 bits)");
+    if (pb->sampling == FLOOD_SAMPLING_RANDOM && pb->k > 65536)
+        return fail(FLOOD_EUNSUPPORTED, "problem: more than 65536 random samples per simplex");
     if (pb->landmarks_in_x != 0 && pb->landmarks_in_x != 1) return fail(FLOOD_EINVAL, "problem: landmarks_in_x must be 0 or 1");
     if (!pb->X || !pb->x_off_d || !pb->Lxyz || !pb->l_off_d) return fail(FLOOD_EINVAL, "problem: NULL device pointer");
     if (pb->landmarks_in_x && !pb->l_xidx) return fail(FLOOD_EINVAL, "problem: landmarks_in_x needs l_xidx");
@@ -88,7 +93,7 @@ flood_status check_problem(const flood_problem *pb) {
     }
     for (int d = 0; d < 4; ++d) {
         const int64_t *so = d == 0 ? pb->l_off : pb->s_off[d];
-        const int64_t nint = flood::n_interior(d, pb->k);
+        const int64_t nint = flood::own_samples(d, pb->k, pb->sampling);
         if (so[pb->B] * nint >= ((int64_t)1 << 31))
             return fail(FLOOD_EUNSUPPORTED, "problem: more than 2^31 - 1 interior samples in one dimension");
         int64_t bk = 0;
@@ -102,6 +107,23 @@ flood_status check_problem(const flood_problem *pb) {
         if (nsimp > 0 && pb->x_off[b + 1] == pb->x_off[b])
             return fail(FLOOD_EINVAL, "problem: a cloud with landmarks has no points");
     }
+    return FLOOD_OK;
+}
+
+flood_status check_outputs(const flood_problem *pb, const flood_outputs *out, const char *name) {
+    if (!out) return fail(FLOOD_EINVAL, std::string(name) + ": outputs are NULL");
+    int with_w = 0, dims = 0;
+    for (int d = 0; d < 4; ++d) {
+        int64_t n = d == 0 ? pb->l_off[pb->B] : pb->s_off[d][pb->B];
+        if (n > 0 && (!out->f[d] || !out->win_x[d] || !out->win_a[d]))
+            return fail(FLOOD_EINVAL, std::string(name) + ": NULL output array");
+        if (n > 0) {
+            ++dims;
+            with_w += out->win_w[d] != nullptr;
+        }
+    }
+    if (with_w != 0 && with_w != dims)
+        return fail(FLOOD_EINVAL, std::string(name) + ": win_w must be given for every dimension or for none");
     return FLOOD_OK;
 }
 
@@ -143,12 +165,8 @@ extern "C" flood_status flood_filtration(const flood_problem *pb, const flood_tu
     flood_tuning t = default_tuning(tune);
     st = check_tuning(t);
     if (st != FLOOD_OK) return st;
-    if (!out) return fail(FLOOD_EINVAL, "flood_filtration: outputs are NULL");
-    for (int d = 0; d < 4; ++d) {
-        int64_t n = d == 0 ? pb->l_off[pb->B] : pb->s_off[d][pb->B];
-        if (n > 0 && (!out->f[d] || !out->win_x[d] || !out->win_a[d]))
-            return fail(FLOOD_EINVAL, "flood_filtration: NULL output array");
-    }
+    st = check_outputs(pb, out, "flood_filtration");
+    if (st != FLOOD_OK) return st;
     size_t need = flood::flood_workspace(pb, t.cells_per_point, nullptr);
     if (!ws || ws_bytes < need)
         return fail(FLOOD_ENOMEM, "flood_filtration: workspace smaller than flood_filtration_workspace_size");
@@ -166,6 +184,8 @@ extern "C" flood_status flood_filtration_backward(const flood_problem *pb, const
         int64_t n = d == 0 ? pb->l_off[pb->B] : pb->s_off[d][pb->B];
         if (n > 0 && grad_f[d] && (!fwd->win_x[d] || !fwd->win_a[d]))
             return fail(FLOOD_EINVAL, "flood_filtration_backward: NULL winner array");
+        if (n > 0 && grad_f[d] && pb->sampling == FLOOD_SAMPLING_RANDOM && !fwd->win_w[d])
+            return fail(FLOOD_EINVAL, "flood_filtration_backward: random sample sets need the winners' weights (win_w)");
     }
     hipError_t e = flood::backward_run(pb, fwd, grad_f, grad_X, grad_L, (hipStream_t)stream);
     return hip_status(e, "flood_filtration_backward");

@@ -91,7 +91,7 @@ __global__ void k_bucket_base(const int64_t *s_off, int32_t B, int64_t n_int, in
     bbase[B] = base;
 }
 
-__global__ void k_sample_keys(int d, int k, int n_int, int32_t B, int64_t S, const float *__restrict__ L,
+__global__ void k_sample_keys(int d, SampleRule rule, int n_int, int32_t B, int64_t S, const float *__restrict__ L,
                               const int32_t *__restrict__ simp, const int64_t *__restrict__ s_off,
                               const GridParam *__restrict__ gp, const int32_t *__restrict__ mbits,
                               const uint32_t *__restrict__ bbase, uint32_t *__restrict__ skey,
@@ -107,13 +107,12 @@ __global__ void k_sample_keys(int d, int k, int n_int, int32_t B, int64_t S, con
         else hi_b = mid;
     }
     const GridParam g = gp[lo_b];
-    int comp[4];
-    if (d == 0) comp[0] = k;
-    else unrank_interior(q, d, k, comp);
+    float w[4];
+    own_weights(rule, d, q, j - s_off[lo_b], w);
     int32_t v[4];
     simplex_vertices(simp, d, j, v);
     float sx, sy, sz;
-    sample_point(L, v, comp, d, k, sx, sy, sz);
+    weighted_point(L, v, w, d, sx, sy, sz);
     const int m = mbits[lo_b];
     const float ext = (float)max(max(g.nx, g.ny), g.nz) * g.h;
     const float sc = (float)(1 << m) / ext;
@@ -140,8 +139,9 @@ struct TileArgs {
     int32_t d, k, n_int, landmarks_in_x;
     int32_t B, radius_budget;  // shells scanned beyond the samples' own cells
     int32_t max_extent;        // tiles whose samples span more cells go straight to phase B
-    int32_t pad;
+    int32_t sampling;
     int64_t n_tiles;
+    uint64_t seed;
 };
 
 __device__ __forceinline__ float box_lb2(float sx, float sy, float sz, float bx0, float bx1, float by0, float by1,
@@ -152,10 +152,13 @@ __device__ __forceinline__ float box_lb2(float sx, float sy, float sz, float bx0
     return ex * ex + ey * ey + ez * ez;
 }
 
+// `always`: vertices publish their value whatever the seed; `own_ties`:
+// random sets, whose own samples win a tie with the facets (the grid's
+// facets hold those samples themselves)
 __device__ __forceinline__ void publish(uint64_t *key, const float *seed, int32_t j, int32_t q, float best,
-                                        bool always) {
+                                        bool always, bool own_ties) {
     const float v = sqrt_rn(best);
-    if (always || v > seed[j]) {
+    if (always || v > seed[j] || (own_ties && v == seed[j])) {
         const uint64_t nk = ((uint64_t)__float_as_uint(v) << 32) | (uint64_t)(0xffffffffu - (uint32_t)q);
         atomicMax((unsigned long long *)&key[j], (unsigned long long)nk);
     }
@@ -212,12 +215,11 @@ __global__ __launch_bounds__(kWaveBlock) __attribute__((amdgpu_waves_per_eu(T ==
             const int q = (int)(gid % (uint32_t)a.n_int);
             sj[t] = (int32_t)j;
             sq[t] = q;
-            int comp[4];
-            if (d == 0) comp[0] = a.k;
-            else unrank_interior(q, d, a.k, comp);
+            float w[4];
+            own_weights(SampleRule{a.k, a.sampling, a.seed}, d, q, j - sbase, w);
             int32_t v[4];
             simplex_vertices(simp, d, j, v);
-            sample_point(L, v, comp, d, a.k, sx[t], sy[t], sz[t]);
+            weighted_point(L, v, w, d, sx[t], sy[t], sz[t]);
             float u = INFINITY;
             if (a.landmarks_in_x) {
                 // the bound is the distance to the landmark's own point of X
@@ -439,7 +441,7 @@ __global__ __launch_bounds__(kWaveBlock) __attribute__((amdgpu_waves_per_eu(T ==
                     // exact minimum: publish (value, rank); x* is found later
                     // for the winning sample only
                     live[t] = false;
-                    if (lane < grp) publish(key, seed, sj[t], sq[t], best[t], d == 0);
+                    if (lane < grp) publish(key, seed, sj[t], sq[t], best[t], d == 0, a.sampling == FLOOD_SAMPLING_RANDOM);
                 } else {
                     const uint64_t kv = __hip_atomic_load(&key[sj[t]], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                     M[t] = fmaxf(M[t], key_value(kv));
@@ -527,6 +529,7 @@ __global__ __launch_bounds__(kWaveBlock) __attribute__((amdgpu_waves_per_eu(T ==
 struct DeepArgs {
     int32_t d, k, n_int, B;
     uint32_t grab;  // queue entries per atomic; 0: kGrab above 2^19 open samples, else kGrabSmall
+    int32_t sampling;
 };
 
 __device__ __forceinline__ void ring_pos(int i, int &r, int &dy, int &dz) {
@@ -726,7 +729,7 @@ __global__ __launch_bounds__(kWaveBlock) __attribute__((amdgpu_waves_per_eu(8, 8
             int32_t bi = 0x7fffffff;
             const bool retired = ring_search<false>(g, cs, occ, xs, sx, sy, sz, bd, bi, a.d > 0, M, &key[j],
                                                     s_p0[wid], s_end[wid], lane, nev);
-            if (!retired && lane == 0) publish(key, seed, (int32_t)j, q, bd, a.d == 0);
+            if (!retired && lane == 0) publish(key, seed, (int32_t)j, q, bd, a.d == 0, a.sampling == FLOOD_SAMPLING_RANDOM);
         }
     }
 #pragma unroll
@@ -738,7 +741,7 @@ __global__ __launch_bounds__(kWaveBlock) __attribute__((amdgpu_waves_per_eu(8, 8
 // x* of the winning own sample of every simplex (one wave per simplex): the
 // value is known, so the search ball is exact and tiny for most simplices
 __global__ __launch_bounds__(kWaveBlock) void k_winner_search(
-    int d, int k, int64_t n, int32_t B, const float *__restrict__ L, const int32_t *__restrict__ simp,
+    int d, SampleRule rule, int64_t n, int32_t B, const float *__restrict__ L, const int32_t *__restrict__ simp,
     const int64_t *__restrict__ s_off, const uint64_t *__restrict__ key, const GridParam *__restrict__ gp,
     const uint32_t *__restrict__ cs, const uint32_t *__restrict__ occ, const float4 *__restrict__ xs,
     int32_t *__restrict__ win_x) {
@@ -749,20 +752,20 @@ __global__ __launch_bounds__(kWaveBlock) void k_winner_search(
     const uint64_t kv = key[j];
     if (kv == 0) return;
     const int q = (int)(0xffffffffu - (uint32_t)(kv & 0xffffffffu));
-    int comp[4];
-    if (d == 0) comp[0] = k;
-    else unrank_interior(q, d, k, comp);
+    const int b = find_cloud(s_off, B, j);
+    float w[4];
+    own_weights(rule, d, q, j - s_off[b], w);
     int32_t v[4];
     simplex_vertices(simp, d, j, v);
     float sx, sy, sz;
-    sample_point(L, v, comp, d, k, sx, sy, sz);
+    weighted_point(L, v, w, d, sx, sy, sz);
     const float val = key_value(kv);
     const float rb = val * (1.0f + 1e-6f) + 1e-30f;
     float bd = rb * rb;
     int32_t bi = 0x7fffffff;
     float M = 0.f;
     unsigned long long nev = 0;
-    const GridParam g = gp[find_cloud(s_off, B, j)];
+    const GridParam g = gp[b];
     ring_search<true>(g, cs, occ, xs, sx, sy, sz, bd, bi, false, M, nullptr, s_p0[wid], s_end[wid], lane, nev);
     if (lane == 0) win_x[j] = bi;
 }
@@ -776,21 +779,33 @@ __device__ __forceinline__ uint32_t pack_comp(const int a[4]) {
     return (uint32_t)a[0] | ((uint32_t)a[1] << 8) | ((uint32_t)a[2] << 16) | ((uint32_t)a[3] << 24);
 }
 
-__global__ void k_winner(int d, int k, int64_t n, const int32_t *__restrict__ simp,
+__global__ void k_winner(int d, SampleRule rule, int64_t n, int32_t B, const int64_t *__restrict__ s_off,
+                         const int32_t *__restrict__ simp,
                          const int32_t *__restrict__ tri_edges, const int32_t *__restrict__ tet_tris,
                          const float *__restrict__ seed, const uint64_t *__restrict__ key, const float *__restrict__ fprev,
                          const int32_t *__restrict__ wxprev, const uint32_t *__restrict__ waprev,
-                         float *__restrict__ f, int32_t *__restrict__ win_x, uint32_t *__restrict__ win_a) {
+                         const float *__restrict__ wwprev, float *__restrict__ f, int32_t *__restrict__ win_x,
+                         uint32_t *__restrict__ win_a, float *__restrict__ win_w) {
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= n) return;
+    const bool random = rule.sampling == FLOOD_SAMPLING_RANDOM;
     const uint64_t kv = key[j];
     if (kv != 0) {
         const int q = (int)(0xffffffffu - (uint32_t)(kv & 0xffffffffu));
-        int comp[4] = {0, 0, 0, 0};
-        if (d == 0) comp[0] = k;
-        else unrank_interior(q, d, k, comp);
-        f[j] = key_value(kv);
-        win_a[j] = pack_comp(comp);  // win_x comes from k_winner_search
+        f[j] = key_value(kv);  // win_x comes from k_winner_search
+        if (random) {
+            win_a[j] = (uint32_t)q | (((1u << (d + 1)) - 1u) << 28);
+        } else {
+            int comp[4] = {0, 0, 0, 0};
+            if (d == 0) comp[0] = rule.k;
+            else unrank_interior(q, d, rule.k, comp);
+            win_a[j] = pack_comp(comp);
+        }
+        if (win_w) {
+            float w[4];
+            own_weights(rule, d, q, j - s_off[find_cloud(s_off, B, j)], w);
+            *(float4 *)&win_w[4 * j] = make_float4(w[0], w[1], w[2], w[3]);
+        }
         return;
     }
     const float sd = seed[j];
@@ -804,12 +819,25 @@ __global__ void k_winner(int d, int k, int64_t n, const int32_t *__restrict__ si
     for (int i = 0; i <= d; ++i)
         if (fprev[fac[i]] == sd) { fi = i; break; }
     const uint32_t pa = waprev[fac[fi]];
-    const int fa[4] = {(int)(pa & 255), (int)((pa >> 8) & 255), (int)((pa >> 16) & 255), (int)(pa >> 24)};
-    int aa[4] = {0, 0, 0, 0};
-    for (int i = 0, src = 0; i <= d; ++i) aa[i] = (i == fi) ? 0 : fa[src++];
     f[j] = sd;
     win_x[j] = wxprev[fac[fi]];
-    win_a[j] = pack_comp(aa);
+    if (random) {
+        // the owner's vertex set: the facet's bits with vertex fi left out
+        const uint32_t m = pa >> 28, lowm = (1u << fi) - 1u;
+        win_a[j] = (pa & 0x0fffffffu) | (((m & lowm) | ((m & ~lowm) << 1)) << 28);
+    } else {
+        const int fa[4] = {(int)(pa & 255), (int)((pa >> 8) & 255), (int)((pa >> 16) & 255), (int)(pa >> 24)};
+        int aa[4] = {0, 0, 0, 0};
+        for (int i = 0, src = 0; i <= d; ++i) aa[i] = (i == fi) ? 0 : fa[src++];
+        win_a[j] = pack_comp(aa);
+    }
+    if (win_w) {
+        const float4 pw = *(const float4 *)&wwprev[4 * (int64_t)fac[fi]];
+        const float fw[4] = {pw.x, pw.y, pw.z, pw.w};
+        float ww[4] = {0.f, 0.f, 0.f, 0.f};
+        for (int i = 0, src = 0; i <= d; ++i) ww[i] = (i == fi) ? 0.f : fw[src++];
+        *(float4 *)&win_w[4 * j] = make_float4(ww[0], ww[1], ww[2], ww[3]);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -827,7 +855,7 @@ size_t flood_workspace(const flood_problem *pb, float alpha, FloodSizes *sz) {
     }
     int64_t smax = 0;
     for (int d = 0; d < 4; ++d) {
-        int64_t sm = n[d] * n_interior(d, pb->k);
+        int64_t sm = n[d] * own_samples(d, pb->k, pb->sampling);
         smax = sm > smax ? sm : smax;
     }
     bytes += sizeof(float) * (nmax + 1) + 256;        // seed
@@ -837,7 +865,7 @@ size_t flood_workspace(const flood_problem *pb, float alpha, FloodSizes *sz) {
     for (int d = 0; d < 4; ++d) {
         int64_t bk = 0;
         const int64_t *so = d == 0 ? pb->l_off : pb->s_off[d];
-        for (int32_t b = 0; b < pb->B; ++b) bk += (int64_t)1 << (3 * morton_bits((so[b + 1] - so[b]) * n_interior(d, pb->k)));
+        for (int32_t b = 0; b < pb->B; ++b) bk += (int64_t)1 << (3 * morton_bits((so[b + 1] - so[b]) * own_samples(d, pb->k, pb->sampling)));
         bkmax = bk > bkmax ? bk : bkmax;
     }
     bytes += 2 * (sizeof(uint32_t) * (smax + 1) + 256);  // sample keys and order
@@ -878,7 +906,7 @@ hipError_t flood_run(const flood_problem *pb, const flood_tuning &tu, const floo
     for (int d = 0; d < 4; ++d) nmax = sz.n[d] > nmax ? sz.n[d] : nmax;
     int64_t smax = 0;
     for (int d = 0; d < 4; ++d) {
-        int64_t sm = sz.n[d] * n_interior(d, pb->k);
+        int64_t sm = sz.n[d] * own_samples(d, pb->k, pb->sampling);
         smax = sm > smax ? sm : smax;
     }
     float *seed = c.take<float>(nmax + 1);
@@ -889,7 +917,7 @@ hipError_t flood_run(const flood_problem *pb, const flood_tuning &tu, const floo
     for (int d = 0; d < 4; ++d) {
         int64_t bk = 0;
         const int64_t *so = d == 0 ? pb->l_off : pb->s_off[d];
-        for (int32_t b = 0; b < pb->B; ++b) bk += (int64_t)1 << (3 * morton_bits((so[b + 1] - so[b]) * n_interior(d, pb->k)));
+        for (int32_t b = 0; b < pb->B; ++b) bk += (int64_t)1 << (3 * morton_bits((so[b + 1] - so[b]) * own_samples(d, pb->k, pb->sampling)));
         bkmax = bk > bkmax ? bk : bkmax;
     }
     uint32_t *skey = c.take<uint32_t>(smax + 1);
@@ -913,7 +941,8 @@ hipError_t flood_run(const flood_problem *pb, const flood_tuning &tu, const floo
     for (int d = 0; d < 4; ++d) {
         const int64_t n = sz.n[d];
         if (n == 0) continue;
-        const int64_t nint = n_interior(d, pb->k);
+        const int64_t nint = own_samples(d, pb->k, pb->sampling);
+        const SampleRule rule{pb->k, pb->sampling, pb->seed};
         const int64_t *soff_h = d == 0 ? pb->l_off : pb->s_off[d];
         const int64_t *soff_d = d == 0 ? pb->l_off_d : pb->s_off_d[d];
         const int32_t *simp = d == 0 ? nullptr : pb->simp[d];
@@ -935,7 +964,7 @@ hipError_t flood_run(const flood_problem *pb, const flood_tuning &tu, const floo
             hipLaunchKernelGGL(k_bucket_base, dim3(1), dim3(1), 0, s, soff_d, pb->B, nint, mbits, bbase);
             e = fill_u32(bcount, 0u, bk + 1, s);
             if (e != hipSuccess) return e;
-            hipLaunchKernelGGL(k_sample_keys, dim3((unsigned)((S + 255) / 256)), dim3(256), 0, s, d, pb->k, (int)nint,
+            hipLaunchKernelGGL(k_sample_keys, dim3((unsigned)((S + 255) / 256)), dim3(256), 0, s, d, rule, (int)nint,
                                pb->B, S, pb->Lxyz, simp, soff_d, g.gp, mbits, bbase, skey, bcount);
             e = exclusive_scan_u32(bcount, bk + 1, bscan, s);
             if (e != hipSuccess) return e;
@@ -952,8 +981,9 @@ hipError_t flood_run(const flood_problem *pb, const flood_tuning &tu, const floo
                 ta.B = pb->B;
                 ta.radius_budget = tu.tile_shells - 1;  // -2 disables the cooperative phase
                 ta.max_extent = tu.tile_extent;
-                ta.pad = 0;
+                ta.sampling = pb->sampling;
                 ta.n_tiles = ntiles;
+                ta.seed = pb->seed;
                 if (out->tile_events[3 * d]) {
                     e = hipEventRecord((hipEvent_t)out->tile_events[3 * d], s);
                     if (e != hipSuccess) return e;
@@ -971,6 +1001,7 @@ hipError_t flood_run(const flood_problem *pb, const flood_tuning &tu, const floo
                 da.n_int = (int32_t)nint;
                 da.B = pb->B;
                 da.grab = (uint32_t)tu.queue_grab;
+                da.sampling = pb->sampling;
                 hipLaunchKernelGGL(k_flood_deep, dim3(2048), dim3(256), 0, s, da, seed, key,
                                    g.gp, g.cell_start, g.occ, g.xs, hard, counters, counters + 8,
                                    (unsigned long long *)out->evals, (unsigned long long *)out->stats);
@@ -980,11 +1011,12 @@ hipError_t flood_run(const flood_problem *pb, const flood_tuning &tu, const floo
                 }
             }
         }
-        hipLaunchKernelGGL(k_winner, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, d, pb->k, n, simp,
-                           pb->tri_edges, pb->tet_tris, seed, key, d > 0 ? out->f[d - 1] : nullptr,
-                           d > 0 ? out->win_x[d - 1] : nullptr, d > 0 ? out->win_a[d - 1] : nullptr, out->f[d],
-                           out->win_x[d], out->win_a[d]);
-        hipLaunchKernelGGL(k_winner_search, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, s, d, pb->k, n, pb->B,
+        hipLaunchKernelGGL(k_winner, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, d, rule, n, pb->B, soff_d,
+                           simp, pb->tri_edges, pb->tet_tris, seed, key, d > 0 ? out->f[d - 1] : nullptr,
+                           d > 0 ? out->win_x[d - 1] : nullptr, d > 0 ? out->win_a[d - 1] : nullptr,
+                           d > 0 ? out->win_w[d - 1] : nullptr, out->f[d], out->win_x[d], out->win_a[d],
+                           out->win_w[d]);
+        hipLaunchKernelGGL(k_winner_search, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, s, d, rule, n, pb->B,
                            pb->Lxyz, simp, soff_d, key, g.gp, g.cell_start, g.occ, g.xs, out->win_x[d]);
         e = hipGetLastError();
         if (e != hipSuccess) return e;

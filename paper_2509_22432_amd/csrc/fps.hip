@@ -464,6 +464,8 @@ __global__ __launch_bounds__(kPT) void k_fps_persist(
 static constexpr int kMaxCpw = 2560;              // chunk slots per workgroup (60 B of LDS each)
 static constexpr int kG = 8;                      // consecutive chunk slots of a workgroup under one group bound
 static constexpr int64_t kCoopMin = 1 << 19;      // clouds of at least this many points
+static constexpr int64_t kCoopMinFew = 1 << 14;   // ... or of this many, in calls of at most kFewClouds clouds
+static constexpr int32_t kFewClouds = 8;
 static constexpr int kSpinLimit = 1 << 22;        // polls of one exchange before the launch gives up
 static constexpr int kK = 2;                      // candidates a workgroup publishes
 static constexpr int kJ = 32;                     // landmarks decided per exchange, at most
@@ -1105,7 +1107,7 @@ struct CoopShape {
 // the cooperative launch of a cloud of n points (one workgroup per CU, at
 // least 16 chunks each); false: the persistent path
 static bool coop_shape(int64_t n, int cus, CoopShape *cs) {
-    if (n < kCoopMin || cus < 1) return false;
+    if (n < kCoopMinFew || cus < 1) return false;
     const int64_t wmax = std::min<int64_t>(cus, kMaxWG);
     for (int l = 0; l <= 3; ++l) {
         const int64_t nc = (n + (64 << l) - 1) / (64 << l);
@@ -1122,8 +1124,9 @@ static bool coop_shape(int64_t n, int cus, CoopShape *cs) {
     return false;
 }
 
-// clouds below this size (and at least kCoopMin) take the cooperative path:
-// their chunk slots fit in LDS with m <= 8 on every workgroup
+// clouds below this size (and at least the call's lower threshold) take the
+// cooperative path: their chunk slots fit in LDS with m <= 8 on every
+// workgroup
 static int64_t coop_limit(int cus) {
     const int64_t wmax = std::min<int64_t>(cus, kMaxWG);
     return std::min<int64_t>((int64_t)1 << 31, wmax * kMaxCpw * 512);
@@ -1148,7 +1151,11 @@ hipError_t fps_run(const float *X, int32_t B, const int64_t *x_off, const int64_
     if (!c.ok()) return hipErrorOutOfMemory;
     const int cus = device_cus();
     const int64_t coop_hi = coop_limit(cus);
-    hipError_t e = grid_build(X, B, x_off, x_off_d, fps_alpha(), w.grid, s, kMaxDim, kCoopMin, coop_hi);
+    // a cloud takes the cooperative launch (all CUs, one cloud at a time)
+    // from kCoopMin points on; in a call of a few clouds already from
+    // kCoopMinFew on, where one workgroup per cloud would leave the GPU idle
+    const int64_t coop_lo = B <= kFewClouds ? kCoopMinFew : kCoopMin;
+    hipError_t e = grid_build(X, B, x_off, x_off_d, fps_alpha(), w.grid, s, kMaxDim, coop_lo, coop_hi);
     if (e != hipSuccess) return e;
     e = fill_f32(w.mind, INFINITY, np, s);
     if (e != hipSuccess) return e;
@@ -1161,7 +1168,7 @@ hipError_t fps_run(const float *X, int32_t B, const int64_t *x_off, const int64_
     for (int32_t b = 0; b < B; ++b) {
         const int64_t n = x_off[b + 1] - x_off[b];
         CoopShape cs;
-        if (n >= kCoopMin && n < coop_hi && coop_shape(n, cus, &cs)) {
+        if (n >= coop_lo && n < coop_hi && coop_shape(n, cus, &cs)) {
             e = fill_u64(rec, 0ull, (int64_t)2 * kMaxWG * kRec, s);
             if (e != hipSuccess) return e;
             e = fill_u64(dec, 0ull, 2 * kDec, s);

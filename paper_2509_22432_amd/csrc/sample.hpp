@@ -59,20 +59,116 @@ __host__ __device__ inline int64_t n_interior(int d, int k) {
     return m * (m - 1) * (m - 2) / 6;
 }
 
-// sample point s = sum_i (a_i/k) v_i in float32 (shared by forward, winner
-// search and backward so all three see the same coordinates)
-__device__ __forceinline__ void sample_point(const float *__restrict__ L, const int32_t *v, const int *a, int d, int k,
-                                             float &sx, float &sy, float &sz) {
-    // w = a_i/k correctly rounded: w = 1 exactly for a vertex sample and
-    // w = 0 terms add nothing, so a vertex sample is the vertex itself
+// s = sum_i w_i v_i in float32, one fused multiply-add per term in vertex
+// order (shared by forward, winner search and backward so all three see the
+// same coordinates; w = 0 terms add nothing, so a face's sample keeps its
+// bits when it is written over the coface's vertices)
+__device__ __forceinline__ void weighted_point(const float *__restrict__ L, const int32_t *v, const float *w, int d,
+                                               float &sx, float &sy, float &sz) {
     sx = 0.f;
     sy = 0.f;
     sz = 0.f;
     for (int i = 0; i <= d; ++i) {
-        const float w = __fdiv_rn((float)a[i], (float)k);
-        sx = __fmaf_rn(w, L[3 * v[i]], sx);
-        sy = __fmaf_rn(w, L[3 * v[i] + 1], sy);
-        sz = __fmaf_rn(w, L[3 * v[i] + 2], sz);
+        sx = __fmaf_rn(w[i], L[3 * v[i]], sx);
+        sy = __fmaf_rn(w[i], L[3 * v[i] + 1], sy);
+        sz = __fmaf_rn(w[i], L[3 * v[i] + 2], sz);
+    }
+}
+
+// grid weights w_i = a_i / k, correctly rounded (w = 1 exactly for a vertex
+// sample, so a vertex sample is the vertex itself)
+__device__ __forceinline__ void grid_weights(const int *a, int d, int k, float w[4]) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) w[i] = i <= d ? __fdiv_rn((float)a[i], (float)k) : 0.f;
+}
+
+// sample point s = sum_i (a_i/k) v_i of the barycentric grid (Lemma 6)
+__device__ __forceinline__ void sample_point(const float *__restrict__ L, const int32_t *v, const int *a, int d, int k,
+                                             float &sx, float &sy, float &sz) {
+    float w[4];
+    grid_weights(a, d, k, w);
+    weighted_point(L, v, w, d, sx, sy, sz);
+}
+
+// ---------------------------------------------------------------------------
+// random sample sets (Thm. 5 holds for any finite P_sigma inside conv sigma;
+// Lemma 9 draws the points uniformly).  Draws come from the counter-based
+// generator Philox4x64-10 (Salmon, Moraes, Dror, Shaw, SC 2011), written
+// from its published definition: sample q of the simplex in cloud-local row
+// r of dimension d uses counter (q, r, d, 0) and key (seed, 0); the top 24
+// bits of words 0..d-1 give uniforms u_i = (word >> 40) 2^-24 (exact in
+// float32), and the spacings of the sorted u_(1) <= .. <= u_(d),
+// (u_(1), u_(2) - u_(1), .., 1 - u_(d)), are uniform on the simplex
+// (Dirichlet(1, .., 1)); every spacing is a multiple of 2^-24 and exact.
+
+__device__ __forceinline__ void philox4x64_10(uint64_t c[4], uint64_t k0, uint64_t k1) {
+    const uint64_t mul0 = 0xD2E7470EE14C6C93ull, mul1 = 0xCA5A826395121157ull;  // round multipliers
+    const uint64_t weyl0 = 0x9E3779B97F4A7C15ull, weyl1 = 0xBB67AE8584CAA73Bull;  // key schedule
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint64_t hi0 = __umul64hi(mul0, c[0]), lo0 = mul0 * c[0];
+        const uint64_t hi1 = __umul64hi(mul1, c[2]), lo1 = mul1 * c[2];
+        const uint64_t x0 = hi1 ^ c[1] ^ k0, x2 = hi0 ^ c[3] ^ k1;
+        c[0] = x0;
+        c[1] = lo1;
+        c[2] = x2;
+        c[3] = lo0;
+        k0 += weyl0;
+        k1 += weyl1;
+    }
+}
+
+__device__ __forceinline__ void random_weights(int d, uint32_t q, int64_t row, uint64_t seed, float w[4]) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) w[i] = 0.f;
+    if (d == 0) {
+        w[0] = 1.f;
+        return;
+    }
+    uint64_t c[4] = {(uint64_t)q, (uint64_t)row, (uint64_t)d, 0ull};
+    philox4x64_10(c, seed, 0ull);
+    float u[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) u[i] = (float)(uint32_t)(c[i] >> 40) * 0x1p-24f;
+    // sort the first d uniforms (d <= 3): a three-element network
+    if (d >= 2 && u[1] < u[0]) { const float t = u[0]; u[0] = u[1]; u[1] = t; }
+    if (d == 3) {
+        if (u[2] < u[1]) { const float t = u[1]; u[1] = u[2]; u[2] = t; }
+        if (u[1] < u[0]) { const float t = u[0]; u[0] = u[1]; u[1] = t; }
+    }
+    w[0] = u[0];
+    for (int i = 1; i < d; ++i) w[i] = u[i] - u[i - 1];
+    w[d] = 1.f - u[d - 1];
+}
+
+// how a simplex's own samples are drawn
+struct SampleRule {
+    int32_t k;         // grid: segments per edge; random: samples per simplex
+    int32_t sampling;  // FLOOD_SAMPLING_GRID or FLOOD_SAMPLING_RANDOM
+    uint64_t seed;     // random sets only
+};
+
+// own samples of a d-simplex: the interior grid points (all a_i >= 1; the
+// boundary points belong to the faces) or the m random points; a vertex owns
+// itself
+__host__ __device__ inline int64_t own_samples(int d, int k, int sampling) {
+    if (d == 0) return 1;
+    return sampling == FLOOD_SAMPLING_RANDOM ? (int64_t)k : n_interior(d, k);
+}
+
+// weights of own sample q of the simplex in cloud-local row `row`
+__device__ __forceinline__ void own_weights(const SampleRule &r, int d, int q, int64_t row, float w[4]) {
+    if (r.sampling == FLOOD_SAMPLING_RANDOM) {
+        random_weights(d, (uint32_t)q, row, r.seed, w);
+    } else {
+        int comp[4];
+        if (d == 0) {
+            comp[0] = r.k;
+            comp[1] = comp[2] = comp[3] = 0;
+        } else {
+            unrank_interior(q, d, r.k, comp);
+        }
+        grid_weights(comp, d, r.k, w);
     }
 }
 

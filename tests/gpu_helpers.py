@@ -10,7 +10,7 @@ def dev():
     return torch.device("cuda:0")
 
 
-def run_single(X, n_lm, k, tuning=None, landmarks=None):
+def run_single(X, n_lm, k, tuning=None, landmarks=None, sampling="grid", seed=0):
     """FPS (GPU) -> Delaunay (host lib) -> flooding (GPU) for one cloud.
     If `landmarks` (float32 [L,3]) is given, they are used instead and are
     not assumed to be points of X."""
@@ -28,11 +28,13 @@ def run_single(X, n_lm, k, tuning=None, landmarks=None):
         Ld = torch.from_numpy(Lxyz).to(dev())
         lx = None
     cx = P.delaunay(Lxyz)
-    pb = P.problem_from_complexes(Xd, [0, len(X)], Ld, [0, len(Lxyz)], [cx], k, l_xidx=lx)
+    pb = P.problem_from_complexes(Xd, [0, len(X)], Ld, [0, len(Lxyz)], [cx], k, l_xidx=lx, sampling=sampling,
+                                  seed=seed)
     run = P.filtration(pb, tuning)
     torch.cuda.synchronize()
     out = dict(f=[t.cpu().numpy() for t in run.f], win_x=[t.cpu().numpy() for t in run.win_x],
-               win_a=[t.cpu().numpy().view(np.uint32) for t in run.win_a], evals=int(run.evals.item()))
+               win_a=[t.cpu().numpy().view(np.uint32) for t in run.win_a],
+               win_w=[t.cpu().numpy() for t in run.win_w], evals=int(run.evals.item()))
     return dict(X=X, Lxyz=Lxyz, idx=idx_h, cx=cx, pb=pb, run=run, out=out)
 
 

@@ -26,7 +26,8 @@ def _maxerr_per_dim(res, ref):
 
 # ---------------------------------------------------------------- landmarks
 
-@pytest.mark.parametrize("cfg,n,L", [(1, None, 64), (2, 200_000, 700), (2, None, 2000), (3, None, 10_000)])
+@pytest.mark.parametrize("cfg,n,L", [(1, None, 64), (2, 12_000, 300), (2, 20_000, 500), (2, 200_000, 700),
+                                     (2, None, 2000), (3, None, 10_000)])
 def test_fps_bitexact(cfg, n, L):
     X = synth.config_cloud(cfg, n)
     print("fps parity cfg", cfg, "N", len(X), "L", L, flush=True)
@@ -51,8 +52,12 @@ def test_fps_lattice_ties_and_start():
         assert np.array_equal(rad.cpu().numpy(), orad)
 
 
-def test_fps_batched_bitexact():
-    clouds, lms = synth.batched_clouds(7, seed=4242, scale=0.2)
+@pytest.mark.parametrize("n_clouds", [7, 12])
+def test_fps_batched_bitexact(n_clouds):
+    # 7 clouds: those of at least 2^14 points take cooperative launches, the
+    # others one workgroup each, in the same call; 12 clouds: all of them
+    # one workgroup each
+    clouds, lms = synth.batched_clouds(n_clouds, seed=4242, scale=0.2)
     x_off = np.concatenate([[0], np.cumsum([len(c) for c in clouds])])
     Xd = torch.from_numpy(np.concatenate(clouds)).to(dev())
     idx, rad = P.fps_batched(Xd, x_off, lms)
@@ -253,3 +258,28 @@ def test_base_tuning_against_oracle_and_metamorphic():
         assert np.array_equal(scaled["out"]["f"][d], np.float32(2) * base["out"]["f"][d]), d
         assert np.array_equal(scaled["out"]["win_a"][d], base["out"]["win_a"][d]), d
         assert np.array_equal(scaled["out"]["win_x"][d], base["out"]["win_x"][d]), d
+
+
+def test_landmark_coordinates_moved_off_their_points():
+    # landmarks_in_x = 1 with coordinates that no longer equal X[l_xidx] (an
+    # optimiser step on Lxyz, say): the per-sample bound is read from X, so
+    # the values stay those of Def. 1 for the moved landmarks, which the
+    # oracle computes by brute force without any bound
+    X = synth.config_cloud(1)
+    k = 4
+    res = run_single(X, 64, k)
+    rng = np.random.default_rng(31)
+    moved = (res["Lxyz"] + rng.normal(0, 0.02, res["Lxyz"].shape)).astype(np.float32)
+    Xd = torch.from_numpy(X).to(dev())
+    pb = P.problem_from_complexes(Xd, [0, len(X)], torch.from_numpy(moved).to(dev()), [0, 64], [res["cx"]], k,
+                                  l_xidx=torch.from_numpy(res["idx"].astype(np.int32)).to(dev()))
+    run = P.filtration(pb)
+    torch.cuda.synchronize()
+    ref = OF.flood_all(X, moved, oracle_complex(res["cx"]), k, "brute")
+    diam = OF.diameter(X)
+    for d in range(4):
+        got = run.f[d].cpu().numpy().astype(np.float64)
+        assert np.abs(got - ref[d][0]).max() <= 1e-5 * diam, d
+        wx = run.win_x[d].cpu().numpy()
+        assert np.all((wx >= 0) & (wx < len(X))), d
+    assert np.all(run.f[0].cpu().numpy() > 0)

@@ -143,3 +143,34 @@ def test_fps_undecided_landmarks_raise():
     with pytest.raises(P.FloodError) as e:
         api.check_landmarks(torch.tensor([0, 5, -1, -1], dtype=torch.int32))
     assert e.value.status == _lib.EHIP and "2 landmark" in str(e.value)
+
+
+def test_sampling_mode_validation():
+    L = _lib.lib()
+    out = _lib.Outputs()
+    for d in range(4):
+        out.f[d] = out.win_x[d] = out.win_a[d] = 0x2000
+    pb = _fake_problem()
+    pb.sampling = 2
+    assert L.flood_filtration(ctypes.byref(pb), None, ctypes.byref(out), None, 0, None) == _lib.EINVAL
+    pb = _fake_problem(k=70000)
+    pb.sampling = _lib.SAMPLING_RANDOM
+    assert L.flood_filtration(ctypes.byref(pb), None, ctypes.byref(out), None, 0, None) == _lib.EUNSUPPORTED
+    # random sets take up to 65536 samples per simplex (the grid stops at k = 255)
+    pb = _fake_problem(k=1000)
+    pb.sampling = _lib.SAMPLING_RANDOM
+    assert L.flood_filtration(ctypes.byref(pb), None, ctypes.byref(out), None, 0, None) == _lib.ENOMEM
+    # win_w for some dimensions only (here vertices and edges exist)
+    five = (ctypes.c_int64 * 2)(0, 5)
+    pb._keep5 = five
+    pb.s_off[1] = ctypes.cast(five, ctypes.POINTER(ctypes.c_int64))
+    pb.simp[1] = pb.s_off_d[1] = 0x1000
+    out.win_w[0] = 0x3000
+    assert L.flood_filtration(ctypes.byref(pb), None, ctypes.byref(out), None, 0, None) == _lib.EINVAL
+    assert "win_w" in L.flood_last_error().decode()
+    # the backward of random sets needs the winners' weights
+    out.win_w[0] = None
+    g = (ctypes.c_void_p * 4)(0x4000, None, None, None)
+    st = L.flood_filtration_backward(ctypes.byref(pb), ctypes.byref(out), g, ctypes.c_void_p(0x5000),
+                                     ctypes.c_void_p(0x6000), None)
+    assert st == _lib.EINVAL and "win_w" in L.flood_last_error().decode()
