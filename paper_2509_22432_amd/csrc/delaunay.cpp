@@ -255,6 +255,13 @@ struct Triangulation {
     std::vector<char> dead;
     std::vector<uint32_t> in_cav, tested;  // insertion id marks
     std::vector<int> free_list;
+    // per-insertion buffers, kept across insertions (no allocation per point)
+    struct EdgeSlot {
+        uint64_t key;
+        int tet, face;
+    };
+    std::vector<int> cavity, stack;
+    std::vector<EdgeSlot> open_edges;
     uint32_t ins = 0;
     int last = 0;
     uint64_t rng = 0x9e3779b97f4a7c15ull;
@@ -332,7 +339,8 @@ struct Triangulation {
         int c0 = locate(q);
         if (!conflict(c0, q)) throw Degenerate();
         ++ins;
-        std::vector<int> cavity, stack;
+        cavity.clear();
+        stack.clear();
         stack.push_back(c0);
         in_cav[c0] = ins;
         tested[c0] = ins;
@@ -351,11 +359,9 @@ struct Triangulation {
             }
         }
         // new tets on the cavity boundary; faces through q are glued by edge
-        struct EdgeSlot {
-            int tet, face;
-        };
-        std::unordered_map<uint64_t, EdgeSlot> edges;
-        edges.reserve(cavity.size() * 6);
+        // (a cavity has a few dozen boundary faces: the still unmatched edges
+        // are searched linearly)
+        open_edges.clear();
         int created_finite = -1;
         for (int c : cavity) {
             for (int i = 0; i < 4; ++i) {
@@ -380,18 +386,20 @@ struct Triangulation {
                         if (k != i && k != j) (m++ == 0 ? e0 : e1) = x.v[k];
                     int lo = std::min(e0, e1), hi = std::max(e0, e1);
                     uint64_t key = ((uint64_t)(uint32_t)(lo + 1) << 32) | (uint32_t)(hi + 1);
-                    auto it = edges.find(key);
-                    if (it == edges.end()) {
-                        edges.emplace(key, EdgeSlot{nt, j});
+                    size_t at = 0;
+                    while (at < open_edges.size() && open_edges[at].key != key) ++at;
+                    if (at == open_edges.size()) {
+                        open_edges.push_back(EdgeSlot{key, nt, j});
                     } else {
-                        t[nt].n[j] = it->second.tet;
-                        t[it->second.tet].n[it->second.face] = nt;
-                        edges.erase(it);
+                        t[nt].n[j] = open_edges[at].tet;
+                        t[open_edges[at].tet].n[open_edges[at].face] = nt;
+                        open_edges[at] = open_edges.back();
+                        open_edges.pop_back();
                     }
                 }
             }
         }
-        if (!edges.empty()) throw Degenerate();
+        if (!open_edges.empty()) throw Degenerate();
         for (int c : cavity) {
             dead[c] = 1;
             free_list.push_back(c);
@@ -566,46 +574,61 @@ extern "C" flood_status flood_delaunay(const float *Lxyz, int32_t L, flood_compl
             cx->T.push_back(r);
         }
         std::sort(cx->T.begin(), cx->T.end());
-        std::vector<std::array<int32_t, 3>> tris;
-        tris.reserve(cx->T.size() * 4);
-        for (auto &r : cx->T)
-            for (int i = 0; i < 4; ++i) {
-                std::array<int32_t, 3> f;
-                for (int k = 0, m = 0; k < 4; ++k)
-                    if (k != i) f[m++] = r[k];
-                tris.push_back(f);
-            }
-        std::sort(tris.begin(), tris.end());
-        tris.erase(std::unique(tris.begin(), tris.end()), tris.end());
-        cx->F = tris;
-        std::vector<std::array<int32_t, 2>> eds;
-        eds.reserve(cx->F.size() * 3);
-        for (auto &f : cx->F)
-            for (int i = 0; i < 3; ++i) {
-                std::array<int32_t, 2> e;
-                for (int k = 0, m = 0; k < 3; ++k)
-                    if (k != i) e[m++] = f[k];
-                eds.push_back(e);
-            }
-        std::sort(eds.begin(), eds.end());
-        eds.erase(std::unique(eds.begin(), eds.end()), eds.end());
-        cx->E = eds;
+        // faces: every facet of every tet as a record (sorted vertices, owner
+        // row, slot); a counting sort by the first vertex and a sort of each
+        // small bucket by the others put equal facets next to each other in
+        // lexicographic order, so a facet's rank is its row, written straight
+        // into the owner's facet map (facet i omits vertex i)
+        struct Rec {
+            int32_t a, b, c, row, slot;
+        };
+        std::vector<Rec> rec, grouped;
+        std::vector<int64_t> start(L + 1);
+        auto group = [&]() {
+            std::fill(start.begin(), start.end(), 0);
+            for (const Rec &r : rec) ++start[r.a + 1];
+            for (int32_t v = 0; v < L; ++v) start[v + 1] += start[v];
+            grouped.resize(rec.size());
+            std::vector<int64_t> cur(start.begin(), start.end() - 1);
+            for (const Rec &r : rec) grouped[cur[r.a]++] = r;
+            for (int32_t v = 0; v < L; ++v)
+                std::sort(grouped.begin() + start[v], grouped.begin() + start[v + 1], [](const Rec &x, const Rec &y) {
+                    return x.b != y.b ? x.b < y.b : x.c < y.c;
+                });
+        };
+        rec.reserve(cx->T.size() * 4);
+        for (size_t j = 0; j < cx->T.size(); ++j) {
+            const auto &r = cx->T[j];
+            rec.push_back(Rec{r[1], r[2], r[3], (int32_t)j, 0});
+            rec.push_back(Rec{r[0], r[2], r[3], (int32_t)j, 1});
+            rec.push_back(Rec{r[0], r[1], r[3], (int32_t)j, 2});
+            rec.push_back(Rec{r[0], r[1], r[2], (int32_t)j, 3});
+        }
+        group();
         cx->tet_tris.resize(cx->T.size());
-        for (size_t j = 0; j < cx->T.size(); ++j)
-            for (int i = 0; i < 4; ++i) {
-                std::array<int32_t, 3> f;
-                for (int k = 0, m = 0; k < 4; ++k)
-                    if (k != i) f[m++] = cx->T[j][k];
-                cx->tet_tris[j][i] = (int32_t)(std::lower_bound(cx->F.begin(), cx->F.end(), f) - cx->F.begin());
-            }
+        cx->F.reserve(grouped.size() / 2 + 8);
+        for (size_t i = 0; i < grouped.size(); ++i) {
+            const Rec &r = grouped[i];
+            if (i == 0 || r.a != grouped[i - 1].a || r.b != grouped[i - 1].b || r.c != grouped[i - 1].c)
+                cx->F.push_back({r.a, r.b, r.c});
+            cx->tet_tris[r.row][r.slot] = (int32_t)cx->F.size() - 1;
+        }
+        rec.clear();
+        rec.reserve(cx->F.size() * 3);
+        for (size_t j = 0; j < cx->F.size(); ++j) {
+            const auto &f = cx->F[j];
+            rec.push_back(Rec{f[1], f[2], 0, (int32_t)j, 0});
+            rec.push_back(Rec{f[0], f[2], 0, (int32_t)j, 1});
+            rec.push_back(Rec{f[0], f[1], 0, (int32_t)j, 2});
+        }
+        group();
         cx->tri_edges.resize(cx->F.size());
-        for (size_t j = 0; j < cx->F.size(); ++j)
-            for (int i = 0; i < 3; ++i) {
-                std::array<int32_t, 2> e;
-                for (int k = 0, m = 0; k < 3; ++k)
-                    if (k != i) e[m++] = cx->F[j][k];
-                cx->tri_edges[j][i] = (int32_t)(std::lower_bound(cx->E.begin(), cx->E.end(), e) - cx->E.begin());
-            }
+        cx->E.reserve(grouped.size() / 3 + 8);
+        for (size_t i = 0; i < grouped.size(); ++i) {
+            const Rec &r = grouped[i];
+            if (i == 0 || r.a != grouped[i - 1].a || r.b != grouped[i - 1].b) cx->E.push_back({r.a, r.b});
+            cx->tri_edges[r.row][r.slot] = (int32_t)cx->E.size() - 1;
+        }
         int64_t euler = (int64_t)L - (int64_t)cx->E.size() + (int64_t)cx->F.size() - (int64_t)cx->T.size();
         std::vector<char> used(L, 0);
         for (auto &r : cx->T)
