@@ -272,6 +272,23 @@ flood_status flood_filtration(const flood_problem *pb, const flood_tuning *tune,
                               const flood_outputs *out, void *ws, size_t ws_bytes, void *stream);
 
 /* ---------------------------------------------------------------------------
+ * flood_filtration without a workspace argument, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  The workspace is a static device array
+ * of FLOOD_STATIC_SCRATCH_BYTES on every device the library runs on, held
+ * until the process ends; the call itself allocates nothing.  Arguments,
+ * results and errors are those of flood_filtration; FLOOD_ENOMEM (before any
+ * launch) when flood_filtration_workspace_size(pb, tune) exceeds the array --
+ * about 700k points at L = N/100 and k = 6.  Every call on a device uses that
+ * device's one array and leaves its contents behind (each call initialises
+ * what it reads), so calls that overlap on one device -- on different
+ * streams or threads -- race and must be serialised by the caller.
+ */
+#define FLOOD_STATIC_SCRATCH_BYTES ((size_t)64 << 20)
+flood_status flood_filtration_noalloc(const flood_problem *pb, const flood_tuning *tune,
+                                      const flood_outputs *out, void *stream);
+
+/* ---------------------------------------------------------------------------
  * Backward of loss(f) through (1), using the winners of a forward call.
  * Away from ties, f(sigma) = ||s* - x*|| with s* = sum_i w_i v_i (grid sets:
  * w_i = a_i/k from win_a; random sets: win_w, which must then be given), so

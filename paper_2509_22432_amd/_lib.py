@@ -66,6 +66,8 @@ def lib():
     L.flood_filtration_workspace_size.argtypes = [P(Problem), P(Tuning)]
     L.flood_filtration.restype = c_i32
     L.flood_filtration.argtypes = [P(Problem), P(Tuning), P(Outputs), c_vp, c_sz, c_vp]
+    L.flood_filtration_noalloc.restype = c_i32
+    L.flood_filtration_noalloc.argtypes = [P(Problem), P(Tuning), P(Outputs), c_vp]
     L.flood_filtration_backward.restype = c_i32
     L.flood_filtration_backward.argtypes = [P(Problem), P(Outputs), c_vp * 4, c_vp, c_vp, c_vp]
     L.flood_persistence.restype = c_i32
@@ -87,5 +89,5 @@ def check(status):
 
 EXPORTED = ["flood_last_error", "flood_fps_workspace_size", "flood_fps", "flood_delaunay",
             "flood_complex_counts", "flood_complex_export", "flood_complex_free",
-            "flood_filtration_workspace_size", "flood_filtration", "flood_filtration_backward",
+            "flood_filtration_workspace_size", "flood_filtration", "flood_filtration_noalloc", "flood_filtration_backward",
             "flood_persistence", "flood_diagram_counts", "flood_diagram_export", "flood_diagram_free"]

@@ -296,9 +296,11 @@ def _tuning(tuning):
 
 class FloodRun:
     """Pre-allocated outputs + workspace for repeated forward calls (and for
-    HIP-graph capture: the call allocates nothing)."""
+    HIP-graph capture: the call allocates nothing).  With noalloc=True no
+    workspace is allocated: the calls go to flood_filtration_noalloc, whose
+    workspace is the library's static device scratch."""
 
-    def __init__(self, pb: FloodProblem, tuning=None, count_evals=True):
+    def __init__(self, pb: FloodProblem, tuning=None, count_evals=True, noalloc=False):
         self.pb = pb
         dev = pb.X.device
         self.tuning = _tuning(tuning)
@@ -318,6 +320,10 @@ class FloodRun:
         o.stats = self.stats.data_ptr() if self.stats is not None else None
         self.out = o
         tp = ctypes.byref(self.tuning) if self.tuning is not None else None
+        self.noalloc = noalloc
+        self.ws, self.ws_bytes = None, 0
+        if noalloc:
+            return
         self.ws_bytes = lib().flood_filtration_workspace_size(ctypes.byref(pb.struct()), tp)
         if self.ws_bytes == 0:
             check(lib().flood_filtration(ctypes.byref(pb.struct()), tp, ctypes.byref(o), None, 0, _stream()))
@@ -325,8 +331,12 @@ class FloodRun:
 
     def __call__(self):
         tp = ctypes.byref(self.tuning) if self.tuning is not None else None
-        check(lib().flood_filtration(ctypes.byref(self.pb.struct()), tp, ctypes.byref(self.out), _ptr(self.ws),
-                                     self.ws_bytes, _stream()))
+        if self.noalloc:
+            check(lib().flood_filtration_noalloc(ctypes.byref(self.pb.struct()), tp, ctypes.byref(self.out),
+                                                 _stream()))
+        else:
+            check(lib().flood_filtration(ctypes.byref(self.pb.struct()), tp, ctypes.byref(self.out),
+                                         _ptr(self.ws), self.ws_bytes, _stream()))
         return self.f
 
     def backward(self, grad_f, grad_X, grad_L):

@@ -1,6 +1,7 @@
 // C ABI of libflood: argument validation (before any launch), workspace
 // queries and error reporting.  Kernels live in the .hip files.
 #include <cmath>
+#include <mutex>
 #include <string>
 
 #include "sample.hpp"
@@ -189,4 +190,57 @@ extern "C" flood_status flood_filtration_backward(const flood_problem *pb, const
     }
     hipError_t e = flood::backward_run(pb, fwd, grad_f, grad_X, grad_L, (hipStream_t)stream);
     return hip_status(e, "flood_filtration_backward");
+}
+
+// ---------------------------------------------------------------------------
+// allocation-free filtration: the workspace is one static device array per
+// device, located once per device with hipGetSymbolAddress (in host code the
+// array's name is not a device address; only the looked-up pointer is used)
+
+static __device__ __align__(256) unsigned char scratch[FLOOD_STATIC_SCRATCH_BYTES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices];
+
+// the current device's scratch address, looked up on the first call there
+hipError_t scratch_ptr(void **ptr) {
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        g_scratch_ptr[dev] = p;
+    }
+    *ptr = g_scratch_ptr[dev];
+    return hipSuccess;
+}
+}  // namespace
+
+extern "C" flood_status flood_filtration_noalloc(const flood_problem *pb, const flood_tuning *tune,
+                                                 const flood_outputs *out, void *stream) {
+    flood_status st = check_problem(pb);
+    if (st != FLOOD_OK) return st;
+    flood_tuning t = default_tuning(tune);
+    st = check_tuning(t);
+    if (st != FLOOD_OK) return st;
+    st = check_outputs(pb, out, "flood_filtration_noalloc");
+    if (st != FLOOD_OK) return st;
+    const size_t need = flood::flood_workspace(pb, t.cells_per_point, nullptr);
+    if (need > FLOOD_STATIC_SCRATCH_BYTES)
+        return fail(FLOOD_ENOMEM, "flood_filtration_noalloc: the problem needs " + std::to_string(need) +
+                                      " bytes of workspace, more than the static scratch of " +
+                                      std::to_string((size_t)FLOOD_STATIC_SCRATCH_BYTES) +
+                                      " bytes; use flood_filtration with a caller workspace");
+    void *ws = nullptr;
+    hipError_t e = scratch_ptr(&ws);
+    if (e != hipSuccess) return hip_status(e, "flood_filtration_noalloc: scratch lookup");
+    e = flood::flood_run(pb, t, out, ws, FLOOD_STATIC_SCRATCH_BYTES, (hipStream_t)stream);
+    return hip_status(e, "flood_filtration_noalloc");
 }

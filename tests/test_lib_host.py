@@ -145,6 +145,23 @@ def test_fps_undecided_landmarks_raise():
     assert e.value.status == _lib.EHIP and "2 landmark" in str(e.value)
 
 
+def test_noalloc_rejects_problems_beyond_the_static_scratch():
+    # a problem whose workspace exceeds the 64 MiB static scratch is refused
+    # before any launch (no GPU needed to see it)
+    pb = _fake_problem(k=6)
+    big = (ctypes.c_int64 * 2)(0, 5_000_000)
+    pb._keep3 = big
+    pb.x_off = ctypes.cast(big, ctypes.POINTER(ctypes.c_int64))
+    out = _lib.Outputs()
+    for d in range(4):
+        out.f[d] = out.win_x[d] = out.win_a[d] = 0x2000
+    L = _lib.lib()
+    assert L.flood_filtration_workspace_size(ctypes.byref(pb), None) > 64 << 20
+    st = L.flood_filtration_noalloc(ctypes.byref(pb), None, ctypes.byref(out), None)
+    assert st == _lib.ENOMEM
+    assert "static scratch" in L.flood_last_error().decode()
+
+
 def test_sampling_mode_validation():
     L = _lib.lib()
     out = _lib.Outputs()
