@@ -272,14 +272,14 @@ def main_block(args, torch, P, synth):
         irun()
         torch.cuda.synchronize()
         ev_runs.append(int(irun.evals.item()))
-        stats_runs.append(irun.stats.view(4, 4).cpu().numpy().copy())
+        stats_runs.append(irun.stats.view(8, 4).cpu().numpy().copy())
     same = all(np.array_equal(irun.f[d].cpu().numpy(), f_gpu[d]) for d in range(4))
     del irun
     ev = int(np.median(ev_runs))
     st = np.median(np.stack(stats_runs), axis=0)
     a_ms = float(np.mean([sum(t[d][0] for d in range(4)) for t in tile_ms]))
     b_ms = float(np.mean([sum(t[d][1] for d in range(4)) for t in tile_ms]))
-    a_ev, b_ev = float(st[:, 2].sum()), float(st[:, 3].sum())
+    a_ev, b_ev = float(st[:4, 2].sum()), float(st[:4, 3].sum())
     dominant = ("k_flood_deep", b_ev, b_ms) if b_ms >= a_ms else ("k_flood_tiles<1>", a_ev, a_ms)
     achieved = FLOP_PER_EVAL * dominant[1] / (dominant[2] * 1e-3) / 1e12
     nsimp = V + E + F + T
@@ -310,9 +310,12 @@ def main_block(args, torch, P, synth):
         "evals_counted_in": "a separate instrumented run (median of 3); the timed steps run without counters",
         "unique_samples_per_dim": n_unique,
         "brute_force_equivalent_evals": int(sum(n_unique)) * len(X),
-        "search_stats_per_dim": {"per_sample_search_samples": [int(v) for v in st[:, 1]],
-                                 "tile_evals": [int(v) for v in st[:, 2]],
-                                 "per_sample_evals": [int(v) for v in st[:, 3]]},
+        "search_stats_per_dim": {"per_sample_search_ring_steps": [int(v) for v in st[:4, 0]],
+                                 "per_sample_search_samples": [int(v) for v in st[:4, 1]],
+                                 "tile_evals": [int(v) for v in st[:4, 2]],
+                                 "tile_lane_utilisation": [float(st[d, 2] / st[4 + d, 0]) if st[4 + d, 0] else None
+                                                           for d in range(4)],
+                                 "per_sample_evals": [int(v) for v in st[:4, 3]]},
         "fps": {"ms": fps_mean, "rounds": args.n_landmarks,
                 "us_per_round": fps_mean * 1e3 / args.n_landmarks,
                 "hbm_frac": (fps_traffic / (fps_mean * 1e-3) / 1e9 / HBM_PEAK_GBS) if fps_traffic else None,
@@ -420,7 +423,7 @@ def batched_block(args, reps):
     gf.replay()
     torch.cuda.synchronize()
     evals = int(gf.run.evals.item())
-    stats = gf.run.stats.view(4, 4).cpu().numpy()
+    stats = gf.run.stats.view(8, 4).cpu().numpy()
     # the same clouds as separate plain calls (one problem per cloud)
     singles = []
     for b in range(len(clouds)):
@@ -448,9 +451,9 @@ def batched_block(args, reps):
            "plain_per_cloud_calls_ms": plain_ms, "plain_clouds_per_s": len(clouds) / (plain_ms * 1e-3),
            "tuning": tuning, "autotune_ms": timings,
            "points": int(pb.x_off[-1]), "landmarks": V, "simplices": n_simp, "evals": evals,
-           "search_stats_per_dim": {"per_sample_search_samples": [int(v) for v in stats[:, 1]],
-                                    "tile_evals": [int(v) for v in stats[:, 2]],
-                                    "per_sample_evals": [int(v) for v in stats[:, 3]]},
+           "search_stats_per_dim": {"per_sample_search_samples": [int(v) for v in stats[:4, 1]],
+                                    "tile_evals": [int(v) for v in stats[:4, 2]],
+                                    "per_sample_evals": [int(v) for v in stats[:4, 3]]},
            "host_prepare_s (fps + delaunay, untimed)": prep_s}
     if not args.no_cpu_baseline:
         out["fp32_vs_fp64"] = batched_errors(clouds, Ls, cxs, pb, f, args.batched_check, args.errors_out)

@@ -232,9 +232,12 @@ typedef struct {
  * of dimension d, between it and the per-sample search, and after the
  * per-sample search (NULL entries are skipped).  grid_events: the same, recorded
  * before and after the grid build.  For profiling only.
- * stats: device uint64 [16] or NULL; receives (+=), for dimension d,
- * [4d+1] samples handed to the per-sample search, [4d+2] evaluations in the
- * cooperative tile search, [4d+3] evaluations in the per-sample search. */
+ * stats: device uint64 [32] or NULL; receives (+=), for dimension d,
+ * [4d] ring steps (64 grid rows each) of the per-sample search, [4d+1]
+ * samples handed to it, [4d+2] evaluations in the cooperative tile search,
+ * [4d+3] evaluations in the per-sample search, [16+4d] sample slots the
+ * tile search evaluated (live or not: its lane utilisation is [4d+2] over
+ * this); [16+4d+1..3] are reserved (zero). */
 typedef struct {
     float *f[4];
     int32_t *win_x[4];

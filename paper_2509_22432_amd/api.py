@@ -309,7 +309,7 @@ class FloodRun:
         self.win_a = [torch.empty(pb.n(d), dtype=torch.int32, device=dev) for d in range(4)]
         self.win_w = [torch.empty((pb.n(d), 4), dtype=torch.float32, device=dev) for d in range(4)]
         self.evals = torch.zeros(1, dtype=torch.int64, device=dev) if count_evals else None
-        self.stats = torch.zeros(16, dtype=torch.int64, device=dev) if count_evals else None
+        self.stats = torch.zeros(32, dtype=torch.int64, device=dev) if count_evals else None
         o = Outputs()
         for d in range(4):
             o.f[d] = self.f[d].data_ptr() if self.f[d].numel() else None

@@ -42,16 +42,20 @@ struct __align__(16) OpenSample {
 // ---------------------------------------------------------------------------
 // per-dimension helpers
 
-// tile offsets per cloud: tiles_b = ceil(n_b * n_int / (64 T))
-__global__ void k_tile_off(const int64_t *s_off, int32_t B, int64_t n_int, int64_t tile_samples, int64_t *tile_off) {
-    if (blockIdx.x != 0 || threadIdx.x != 0) return;
-    int64_t t = 0;
-    for (int32_t b = 0; b < B; ++b) {
-        tile_off[b] = t;
-        int64_t S = (s_off[b + 1] - s_off[b]) * n_int;
-        t += (S + tile_samples - 1) / tile_samples;
+// tile offsets per cloud: tiles_b = ceil(n_b * n_int / (64 T)) (one block,
+// a thread per cloud in rounds)
+__global__ __launch_bounds__(1024) void k_tile_off(const int64_t *s_off, int32_t B, int64_t n_int,
+                                                    int64_t tile_samples, int64_t *tile_off) {
+    int64_t carry = 0;
+    for (int32_t b0 = 0; b0 < B; b0 += (int32_t)blockDim.x) {
+        const int32_t b = b0 + (int32_t)threadIdx.x;
+        const int64_t S = b < B ? (s_off[b + 1] - s_off[b]) * n_int : 0;
+        int64_t total;
+        const int64_t off = block_exclusive_i64((S + tile_samples - 1) / tile_samples, total);
+        if (b < B) tile_off[b] = carry + off;
+        carry += total;
     }
-    tile_off[B] = t;
+    if (threadIdx.x == 0) tile_off[B] = carry;
 }
 
 // seed = max over facets (facet i omits vertex i); 0 for vertices
@@ -79,16 +83,21 @@ __device__ __forceinline__ float key_value(uint64_t kv) { return __uint_as_float
 // four samples per bucket), so that 64 consecutive samples form a compact
 // tile whatever simplices they come from.
 
-__global__ void k_bucket_base(const int64_t *s_off, int32_t B, int64_t n_int, int32_t *mbits, uint32_t *bbase) {
-    if (blockIdx.x != 0 || threadIdx.x != 0) return;
-    uint32_t base = 0;
-    for (int32_t b = 0; b < B; ++b) {
-        const int m = morton_bits((s_off[b + 1] - s_off[b]) * n_int);
-        mbits[b] = m;
-        bbase[b] = base;
-        base += 1u << (3 * m);
+__global__ __launch_bounds__(1024) void k_bucket_base(const int64_t *s_off, int32_t B, int64_t n_int, int32_t *mbits,
+                                                       uint32_t *bbase) {
+    int64_t carry = 0;
+    for (int32_t b0 = 0; b0 < B; b0 += (int32_t)blockDim.x) {
+        const int32_t b = b0 + (int32_t)threadIdx.x;
+        const int m = b < B ? morton_bits((s_off[b + 1] - s_off[b]) * n_int) : 0;
+        int64_t total;
+        const int64_t off = block_exclusive_i64(b < B ? (int64_t)1 << (3 * m) : 0, total);
+        if (b < B) {
+            mbits[b] = m;
+            bbase[b] = (uint32_t)(carry + off);
+        }
+        carry += total;
     }
-    bbase[B] = base;
+    if (threadIdx.x == 0) bbase[B] = (uint32_t)carry;
 }
 
 __global__ void k_sample_keys(int d, SampleRule rule, int n_int, int32_t B, int64_t S, const float *__restrict__ L,
@@ -260,7 +269,7 @@ __global__ __launch_bounds__(kWaveBlock) __attribute__((amdgpu_waves_per_eu(T ==
         lo[ax] = __builtin_amdgcn_readfirstlane(lo[ax]);
         hi[ax] = __builtin_amdgcn_readfirstlane(hi[ax]);
     }
-    unsigned long long nev = 0;
+    unsigned long long nev = 0, nslot = 0;  // evaluations of live samples; of all the tile's sample slots
     // lanes [0, grp) hold the tile's samples; with grp < 64 (one sample per
     // lane only) lane l holds a copy of lane l mod grp's sample and scans its
     // share of every staged pass, and the copies' minima are combined after
@@ -343,6 +352,9 @@ __global__ __launch_bounds__(kWaveBlock) __attribute__((amdgpu_waves_per_eu(T ==
                         if (__any(need)) need_m |= 1ull << src;
                     }
                     if (!need_m) continue;
+                    int nlive = 0;
+#pragma unroll
+                    for (int t = 0; t < T; ++t) nlive += __popcll(__ballot(live[t] && lane < grp));
                     // the kept runs' points, flattened: 64 per coalesced load,
                     // staged in LDS and read back at one address by every lane
                     const uint32_t cnt = ((need_m >> lane) & 1ull) ? p1 - p0 : 0u;
@@ -350,10 +362,8 @@ __global__ __launch_bounds__(kWaveBlock) __attribute__((amdgpu_waves_per_eu(T ==
                     const uint32_t total = rd_lane(incl, 63);
                     sw_p0[lane] = p0;
                     sw_end[lane] = incl;
-                    int nlive = 0;
-#pragma unroll
-                    for (int t = 0; t < T; ++t) nlive += __popcll(__ballot(live[t] && lane < grp));
                     nev += (unsigned long long)total * (unsigned long long)nlive;
+                    nslot += (unsigned long long)total * (unsigned long long)(T * grp);
                     __builtin_amdgcn_wave_barrier();
                     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
                     // kStage points per pass (kStage / 64 per lane); the next
@@ -513,6 +523,7 @@ __global__ __launch_bounds__(kWaveBlock) __attribute__((amdgpu_waves_per_eu(T ==
     }
     if (evals && lane == 0 && nev) atomicAdd(evals, nev);
     if (stats && lane == 0 && nev) atomicAdd(&stats[4 * d + 2], nev);
+    if (stats && lane == 0 && nslot) atomicAdd(&stats[16 + 4 * d], nslot);
 }
 
 // ---------------------------------------------------------------------------
@@ -571,7 +582,7 @@ __device__ bool ring_search(const GridParam &g, const uint32_t *__restrict__ cs,
                             const float4 *__restrict__ xs,
                             float sx, float sy, float sz, float &bd, int32_t &bi, bool retire, float &M,
                             const uint64_t *__restrict__ keyj, uint32_t *s_p0, uint32_t *s_end, int lane,
-                            unsigned long long &nev) {
+                            unsigned long long &nev, uint32_t &steps) {
     if (retire && sqrt_rn(bd) < M) return true;
     const int cy = cell_of(sy, g.oy, g.inv_h, g.ny), cz = cell_of(sz, g.oz, g.inv_h, g.nz);
     const int rmax = max(max(cy, g.ny - 1 - cy), max(cz, g.nz - 1 - cz));
@@ -611,6 +622,7 @@ __device__ bool ring_search(const GridParam &g, const uint32_t *__restrict__ cs,
         float lbd = bd;
         int32_t lbi = bi;
         if (lane == 0) nev += total;
+        ++steps;
         for (uint32_t k0 = (uint32_t)lane * kU; k0 < total; k0 += 64 * kU) {
             int rr = 0, hi_r = 63;  // first row whose inclusive end exceeds k0
             while (rr < hi_r) {
@@ -689,6 +701,7 @@ __global__ __launch_bounds__(kWaveBlock) __attribute__((amdgpu_waves_per_eu(8, 8
     const uint32_t n = *queue_count;
     if (stats && blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(&stats[4 * a.d + 1], (unsigned long long)n);
     unsigned long long nev = 0;
+    uint32_t nsteps = 0;  // ring steps (64 rows each) of this wave
     // workgroups are dispatched to the 8 XCDs round-robin; each XCD takes the
     // queue segments x, x+8, ... through its own counter, so neighbouring
     // samples (same tile, same grid rows) meet in one L2
@@ -728,7 +741,7 @@ __global__ __launch_bounds__(kWaveBlock) __attribute__((amdgpu_waves_per_eu(8, 8
             const int q = (int)(gid % (uint32_t)a.n_int);
             int32_t bi = 0x7fffffff;
             const bool retired = ring_search<false>(g, cs, occ, xs, sx, sy, sz, bd, bi, a.d > 0, M, &key[j],
-                                                    s_p0[wid], s_end[wid], lane, nev);
+                                                    s_p0[wid], s_end[wid], lane, nev, nsteps);
             if (!retired && lane == 0) publish(key, seed, (int32_t)j, q, bd, a.d == 0, a.sampling == FLOOD_SAMPLING_RANDOM);
         }
     }
@@ -736,6 +749,7 @@ __global__ __launch_bounds__(kWaveBlock) __attribute__((amdgpu_waves_per_eu(8, 8
     for (int o = 32; o > 0; o >>= 1) nev += __shfl_xor(nev, o, 64);
     if (evals && lane == 0 && nev) atomicAdd(evals, nev);
     if (stats && lane == 0 && nev) atomicAdd(&stats[4 * a.d + 3], nev);
+    if (stats && lane == 0 && nsteps) atomicAdd(&stats[4 * a.d], (unsigned long long)nsteps);
 }
 
 // x* of the winning own sample of every simplex (one wave per simplex): the
@@ -765,8 +779,10 @@ __global__ __launch_bounds__(kWaveBlock) void k_winner_search(
     int32_t bi = 0x7fffffff;
     float M = 0.f;
     unsigned long long nev = 0;
+    uint32_t nsteps = 0;
     const GridParam g = gp[b];
-    ring_search<true>(g, cs, occ, xs, sx, sy, sz, bd, bi, false, M, nullptr, s_p0[wid], s_end[wid], lane, nev);
+    ring_search<true>(g, cs, occ, xs, sx, sy, sz, bd, bi, false, M, nullptr, s_p0[wid], s_end[wid], lane, nev,
+                      nsteps);
     if (lane == 0) win_x[j] = bi;
 }
 
@@ -956,12 +972,12 @@ hipError_t flood_run(const flood_problem *pb, const flood_tuning &tu, const floo
             const int64_t tsamp = 64 * (int64_t)T;
             int64_t ntiles = 0;
             for (int32_t b = 0; b < pb->B; ++b) ntiles += ((soff_h[b + 1] - soff_h[b]) * nint + tsamp - 1) / tsamp;
-            hipLaunchKernelGGL(k_tile_off, dim3(1), dim3(1), 0, s, soff_d, pb->B, nint, tsamp, tile_off[d]);
+            hipLaunchKernelGGL(k_tile_off, dim3(1), dim3(1024), 0, s, soff_d, pb->B, nint, tsamp, tile_off[d]);
             // spatial order of the samples
             int64_t bk = 0;
             for (int32_t b = 0; b < pb->B; ++b) bk += (int64_t)1 << (3 * morton_bits((soff_h[b + 1] - soff_h[b]) * nint));
             const int64_t S = n * nint;
-            hipLaunchKernelGGL(k_bucket_base, dim3(1), dim3(1), 0, s, soff_d, pb->B, nint, mbits, bbase);
+            hipLaunchKernelGGL(k_bucket_base, dim3(1), dim3(1024), 0, s, soff_d, pb->B, nint, mbits, bbase);
             e = fill_u32(bcount, 0u, bk + 1, s);
             if (e != hipSuccess) return e;
             hipLaunchKernelGGL(k_sample_keys, dim3((unsigned)((S + 255) / 256)), dim3(256), 0, s, d, rule, (int)nint,

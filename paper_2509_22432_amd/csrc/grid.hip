@@ -318,62 +318,75 @@ __global__ __launch_bounds__(kBlock) void k_bbox_final(const float *part, int nb
         }
 }
 
-// one thread: grid parameters of every cloud (sequential prefix of the cell bases)
-__global__ void k_grid_params(const uint32_t *bbox, const int64_t *x_off, int32_t B, float alpha, int32_t max_dim,
-                              int64_t morton_lo, int64_t morton_hi, int32_t shift, GridParam *gp, int64_t *bk_off) {
-    if (blockIdx.x != 0 || threadIdx.x != 0) return;
-    int64_t base = 0;
-    bk_off[0] = 0;
-    for (int32_t b = 0; b < B; ++b) {
+// grid parameters of every cloud, one thread per cloud in rounds of a
+// block; the cell bases and bucket offsets are prefix sums over the clouds
+__global__ __launch_bounds__(1024) void k_grid_params(const uint32_t *bbox, const int64_t *x_off, int32_t B,
+                                                       float alpha, int32_t max_dim, int64_t morton_lo,
+                                                       int64_t morton_hi, int32_t shift, GridParam *gp,
+                                                       int64_t *bk_off) {
+    int64_t cell_carry = 0, bk_carry = 0;
+    for (int32_t b0 = 0; b0 < B; b0 += (int32_t)blockDim.x) {
+        const int32_t b = b0 + (int32_t)threadIdx.x;
         GridParam g;
-        int64_t n = x_off[b + 1] - x_off[b];
-        int64_t cap = cells_cap(n, alpha);
-        float lo[3], hi[3], e[3];
-        float emax = 0.f, amax = 0.f;
-        for (int a = 0; a < 3; ++a) {
-            lo[a] = key_float(bbox[6 * b + a]);
-            hi[a] = key_float(bbox[6 * b + 3 + a]);
-            if (!(lo[a] <= hi[a])) { lo[a] = 0.f; hi[a] = 0.f; }  // empty cloud or non-finite data
-            e[a] = hi[a] - lo[a];
-            emax = fmaxf(emax, e[a]);
-            amax = fmaxf(amax, fmaxf(fabsf(lo[a]), fabsf(hi[a])));
-        }
-        if (!(emax > 0.f)) emax = 1.f;
-        double target = (double)(cap - 64) > 1.0 ? (double)(cap - 64) : 1.0;
-        double vol = 1.0;
-        for (int a = 0; a < 3; ++a) vol *= fmax((double)e[a], 1e-7 * (double)emax);
-        double h = cbrt(vol / target);
-        if (!(h > 0.0)) h = emax;
-        int64_t nx, ny, nz;
-        g.morton = (n >= morton_lo && n < morton_hi) ? 1 : 0;
-        if (g.morton) {
-            // a 2^m cube over the largest extent, 8^m <= cap - 64 cells
-            int m = 0;
-            while (m < 10 && ((int64_t)8 << (3 * m)) <= cap - 64 && ((int64_t)2 << m) <= max_dim) ++m;
-            nx = ny = nz = (int64_t)1 << m;
-            h = (double)emax / (double)nx;
-        } else {
-            for (int it = 0; it < 4096; ++it) {
-                nx = (int64_t)floor((double)e[0] / h) + 1;
-                ny = (int64_t)floor((double)e[1] / h) + 1;
-                nz = (int64_t)floor((double)e[2] / h) + 1;
-                if (nx <= max_dim && ny <= max_dim && nz <= max_dim && nx * ny * nz <= cap) break;
-                h *= 1.05;
+        int64_t cap = 0, nbk = 0;
+        if (b < B) {
+            int64_t n = x_off[b + 1] - x_off[b];
+            cap = cells_cap(n, alpha);
+            nbk = (cap + (1ll << shift) - 1) >> shift;
+            float lo[3], hi[3], e[3];
+            float emax = 0.f, amax = 0.f;
+            for (int a = 0; a < 3; ++a) {
+                lo[a] = key_float(bbox[6 * b + a]);
+                hi[a] = key_float(bbox[6 * b + 3 + a]);
+                if (!(lo[a] <= hi[a])) { lo[a] = 0.f; hi[a] = 0.f; }  // empty cloud or non-finite data
+                e[a] = hi[a] - lo[a];
+                emax = fmaxf(emax, e[a]);
+                amax = fmaxf(amax, fmaxf(fabsf(lo[a]), fabsf(hi[a])));
             }
+            if (!(emax > 0.f)) emax = 1.f;
+            double target = (double)(cap - 64) > 1.0 ? (double)(cap - 64) : 1.0;
+            double vol = 1.0;
+            for (int a = 0; a < 3; ++a) vol *= fmax((double)e[a], 1e-7 * (double)emax);
+            double h = cbrt(vol / target);
+            if (!(h > 0.0)) h = emax;
+            int64_t nx = 1, ny = 1, nz = 1;
+            g.morton = (n >= morton_lo && n < morton_hi) ? 1 : 0;
+            if (g.morton) {
+                // a 2^m cube over the largest extent, 8^m <= cap - 64 cells
+                int m = 0;
+                while (m < 10 && ((int64_t)8 << (3 * m)) <= cap - 64 && ((int64_t)2 << m) <= max_dim) ++m;
+                nx = ny = nz = (int64_t)1 << m;
+                h = (double)emax / (double)nx;
+            } else {
+                for (int it = 0; it < 4096; ++it) {
+                    nx = (int64_t)floor((double)e[0] / h) + 1;
+                    ny = (int64_t)floor((double)e[1] / h) + 1;
+                    nz = (int64_t)floor((double)e[2] / h) + 1;
+                    if (nx <= max_dim && ny <= max_dim && nz <= max_dim && nx * ny * nz <= cap) break;
+                    h *= 1.05;
+                }
+            }
+            g.ox = lo[0]; g.oy = lo[1]; g.oz = lo[2];
+            g.h = (float)h;
+            g.inv_h = (float)(1.0 / h);
+            g.eps = 1e-3f * (float)h + 1e-6f * amax;
+            g.nx = (int32_t)nx; g.ny = (int32_t)ny; g.nz = (int32_t)nz;
+            g.pt_base = x_off[b];
+            g.npts = n;
+            g.cells_cap = cap;
         }
-        g.ox = lo[0]; g.oy = lo[1]; g.oz = lo[2];
-        g.h = (float)h;
-        g.inv_h = (float)(1.0 / h);
-        g.eps = 1e-3f * (float)h + 1e-6f * amax;
-        g.nx = (int32_t)nx; g.ny = (int32_t)ny; g.nz = (int32_t)nz;
-        g.cell_base = base;
-        g.pt_base = x_off[b];
-        g.npts = n;
-        g.cells_cap = cap;
-        gp[b] = g;
-        base += cap;
-        bk_off[b + 1] = bk_off[b] + ((cap + (1ll << shift) - 1) >> shift);
+        int64_t cells_total, bk_total;
+        const int64_t cell_off = block_exclusive_i64(cap, cells_total);
+        const int64_t bk_of = block_exclusive_i64(nbk, bk_total);
+        if (b < B) {
+            g.cell_base = cell_carry + cell_off;
+            gp[b] = g;
+            bk_off[b] = bk_carry + bk_of;
+        }
+        cell_carry += cells_total;
+        bk_carry += bk_total;
     }
+    if (threadIdx.x == 0) bk_off[B] = bk_carry;
 }
 
 
@@ -562,7 +575,7 @@ hipError_t grid_build(const float *X, int32_t B, const int64_t *x_off, const int
     if (g.bx < 1) return hipErrorInvalidValue;  // a cloud with more cells than the partition supports
     hipLaunchKernelGGL(k_bbox, dim3(g.bbox_blocks, B), dim3(kBlock), 0, s, X, x_off_d, g.bbox_part);
     hipLaunchKernelGGL(k_bbox_final, dim3(B), dim3(kBlock), 0, s, g.bbox_part, g.bbox_blocks, g.bbox);
-    hipLaunchKernelGGL(k_grid_params, dim3(1), dim3(1), 0, s, g.bbox, x_off_d, B, alpha, max_dim, morton_lo, morton_hi,
+    hipLaunchKernelGGL(k_grid_params, dim3(1), dim3(1024), 0, s, g.bbox, x_off_d, B, alpha, max_dim, morton_lo, morton_hi,
                        g.shift, g.gp, g.bk_off);
     hipError_t e = fill_u32(g.bstart, 0u, g.nbtot + 1, s);
     if (e != hipSuccess) return e;

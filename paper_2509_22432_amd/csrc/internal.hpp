@@ -46,6 +46,30 @@ __host__ __device__ inline int64_t cells_cap(int64_t n, float alpha) {
     return (int64_t)c + 1 + 64;
 }
 
+// Exclusive prefix sum over a block: thread t passes v (its item's value)
+// and receives the sum of the values of threads 0..t-1; every thread gets
+// the block total.  Called by every thread of a block of at most 1024.
+__device__ inline int64_t block_exclusive_i64(int64_t v, int64_t &total) {
+    __shared__ int64_t s_part[1024];
+    __shared__ int64_t s_total;
+    s_part[threadIdx.x] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int64_t acc = 0;
+        for (unsigned t = 0; t < blockDim.x; ++t) {
+            const int64_t x = s_part[t];
+            s_part[t] = acc;
+            acc += x;
+        }
+        s_total = acc;
+    }
+    __syncthreads();
+    const int64_t r = s_part[threadIdx.x];
+    total = s_total;
+    __syncthreads();
+    return r;
+}
+
 // Ordered-key encoding of floats for atomic min/max on unsigned ints.
 __device__ inline uint32_t float_key(float f) {
     uint32_t u = __float_as_uint(f);

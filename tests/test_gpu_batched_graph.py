@@ -48,7 +48,7 @@ def b512():
     gf.replay()
     torch.cuda.synchronize()
     r1 = _snap(gf.run)
-    open_samples = gf.run.stats.view(4, 4)[:, 1].cpu().numpy().copy()
+    open_samples = gf.run.stats.view(8, 4)[:4, 1].cpu().numpy().copy()
     eager = P.filtration(pb)
     torch.cuda.synchronize()
     ref = _snap(eager)
@@ -70,6 +70,17 @@ def test_long_queue_branch_taken_and_grab_invariant(b512):
         run = P.filtration(b512["pb"], {"queue_grab": grab}, count_evals=False)
         torch.cuda.synchronize()
         _same(_snap(run), b512["ref"], "queue_grab %d" % grab)
+        del run
+
+
+def test_every_autotuner_candidate_gives_the_same_bits(b512):
+    # the benchmark replays the tuning the autotuner picks; every candidate
+    # it may pick computes the same values and winners
+    from paper_2509_22432_amd import autotune
+    for cand in autotune.DEFAULT_CANDIDATES:
+        run = P.filtration(b512["pb"], cand, count_evals=False)
+        torch.cuda.synchronize()
+        _same(_snap(run), b512["ref"], str(cand))
         del run
 
 
