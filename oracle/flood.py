@@ -211,14 +211,19 @@ def r_exact(X, V):
 
 def diameter(X) -> float:
     """diam(X): the largest pairwise distance, exactly over the convex-hull
-    vertices (FP64)."""
+    vertices (FP64).  Coordinates that are constant over X (a planar cloud
+    stored with z = 0) are left out of the hull, which then lives in the
+    remaining coordinates; the distances are unchanged."""
     X = _as_f64(X)
-    if len(X) <= 3:
+    Xh = X[:, np.ptp(X, axis=0) > 0] if len(X) else X
+    if len(X) <= 3 or Xh.shape[1] == 0:
         idx = np.arange(len(X))
+    elif Xh.shape[1] == 1:
+        idx = np.array([int(np.argmin(Xh[:, 0])), int(np.argmax(Xh[:, 0]))])
     else:
         from scipy.spatial import ConvexHull
         try:
-            idx = ConvexHull(X).vertices
+            idx = ConvexHull(Xh).vertices
         except Exception:
             idx = np.arange(len(X))
     H = X[idx]

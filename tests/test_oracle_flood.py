@@ -235,6 +235,18 @@ def test_diameter_known_shapes():
     assert FL.diameter(4.0 * X) == 4.0 * FL.diameter(X)
 
 
+def test_diameter_of_planar_clouds():
+    # a planar cloud stored with z = 0 (ambient dimension 2): the hull is
+    # taken in the plane; a cloud on a tilted plane falls back to all pairs
+    P2 = synth.planar_cheese(500, 4, seed=7)
+    X = np.zeros((len(P2), 3))
+    X[:, :2] = P2
+    assert abs(FL.diameter(X) - _diam_brute(X)) <= 1e-15 * _diam_brute(X)
+    rng = np.random.default_rng(8)
+    T = rng.random((300, 2)) @ np.array([[1.0, 0.2, 0.5], [0.1, 1.0, -0.3]])
+    assert abs(FL.diameter(T) - _diam_brute(T)) <= 1e-15 * _diam_brute(T)
+
+
 def test_diameter_of_the_torus_workload():
     # R = 1, r = 0.3: the outer equator has diameter 2 (R + r) = 2.6; the
     # noise (sigma = 0.01) moves it by a few sigma at most
