@@ -312,6 +312,8 @@ def main_block(args, torch, P, synth):
         "brute_force_equivalent_evals": int(sum(n_unique)) * len(X),
         "search_stats_per_dim": {"per_sample_search_ring_steps": [int(v) for v in st[:4, 0]],
                                  "per_sample_search_samples": [int(v) for v in st[:4, 1]],
+                                 "per_sample_search_longest_steps": [int(v) for v in st[4:, 1]],
+                                 "per_sample_searches_over_32_steps": [int(v) for v in st[4:, 2]],
                                  "tile_evals": [int(v) for v in st[:4, 2]],
                                  "tile_lane_utilisation": [float(st[d, 2] / st[4 + d, 0]) if st[4 + d, 0] else None
                                                            for d in range(4)],

@@ -107,6 +107,15 @@ flood_status flood_fps(const float *X, int32_t B, const int64_t *x_off, const in
  */
 typedef struct flood_complex flood_complex;
 flood_status flood_delaunay(const float *Lxyz, int32_t L, flood_complex **out);
+/* The same in ambient dimension 2 (Sec. 5.2 varies the ambient dimension):
+ * Lxy host float [L][2], L >= 3; the complex has vertices, edges and
+ * triangles only (no tetrahedra, tets / tet_tris export nothing), with
+ * orientation and in-circle predicates evaluated exactly.  EDEGENERATE:
+ * fewer than 3 non-collinear points, duplicates, or an exactly cocircular
+ * configuration that decides the triangulation.  The flooding entry points
+ * take such a complex with the points and landmarks as [n][3] rows whose
+ * third coordinate is 0. */
+flood_status flood_delaunay2d(const float *Lxy, int32_t L, flood_complex **out);
 /* counts[0..3] = vertices, edges, triangles, tetrahedra; counts[4] = exact
  * predicate fallbacks taken (diagnostic). */
 flood_status flood_complex_counts(const flood_complex *cx, int64_t counts[5]);
@@ -237,7 +246,9 @@ typedef struct {
  * samples handed to it, [4d+2] evaluations in the cooperative tile search,
  * [4d+3] evaluations in the per-sample search, [16+4d] sample slots the
  * tile search evaluated (live or not: its lane utilisation is [4d+2] over
- * this); [16+4d+1..3] are reserved (zero). */
+ * this), [16+4d+1] the most ring steps of one per-sample search, [16+4d+2]
+ * per-sample searches of more than 32 ring steps; [16+4d+3] is reserved
+ * (zero). */
 typedef struct {
     float *f[4];
     int32_t *win_x[4];

@@ -16,12 +16,15 @@ play are rejected here (DegenerateInput).
   landmark is used.  A locally Delaunay triangulation of the hull is the
   Delaunay triangulation (Delaunay's lemma), unique in general position.
 * ``faces``: the closure -- sorted edge and triangle lists and face maps.
+* In the plane (ambient dimension 2, Sec. 5.2): ``brute_tris`` (empty
+  circumcircles), ``certify2d`` (every interior edge locally Delaunay, hull
+  edges supporting, Euler characteristic 1) and ``faces2d``.
 """
 from itertools import combinations
 
 import numpy as np
 
-from .predicates import insph_sign, orient_sign
+from .predicates import incircle_sign, insph_sign, orient2_sign, orient_sign
 
 
 class DegenerateInput(ValueError):
@@ -138,3 +141,91 @@ def qhull_tets(P: np.ndarray) -> np.ndarray:
     """scipy's qhull Delaunay, canonicalised -- an independent cross-check."""
     from scipy.spatial import Delaunay
     return canonical(Delaunay(np.asarray(P, dtype=np.float64)).simplices)
+
+
+# --------------------------------------------------------------------------
+# the plane
+
+
+def canonical2(F: np.ndarray) -> np.ndarray:
+    F = np.sort(np.asarray(F, dtype=np.int64), axis=1)
+    if len(F) == 0:
+        return F.reshape(0, 3)
+    return F[np.lexsort(F.T[::-1])]
+
+
+def brute_tris(P: np.ndarray) -> np.ndarray:
+    """Every triple with non-zero orientation whose open circumcircle holds
+    no other point.  O(L^4); tiny inputs only."""
+    P = np.asarray(P, dtype=np.float64)
+    n = P.shape[0]
+    tri = np.array(list(combinations(range(n), 3)), dtype=np.int64)
+    o, _ = orient2_sign(P[tri[:, 0]], P[tri[:, 1]], P[tri[:, 2]])
+    if np.any(o == 0):
+        raise DegenerateInput("collinear triple")
+    member = np.zeros((len(tri), n), dtype=bool)
+    member[np.arange(len(tri))[:, None], tri] = True
+    s, _ = incircle_sign(P[tri[:, 0]][:, None], P[tri[:, 1]][:, None], P[tri[:, 2]][:, None], P[None, :, :],
+                         skip=member)
+    inside = s.astype(np.int64) * o.astype(np.int64)[:, None]
+    if np.any((s == 0) & ~member):
+        raise DegenerateInput("cocircular 4-subset")
+    empty = ~np.any((inside > 0) & ~member, axis=1)
+    return canonical2(tri[empty])
+
+
+def faces2d(F: np.ndarray):
+    """(E [nE,2], tri_edges [nF,3]) of a triangle list, rows sorted; edge i of
+    a triangle is the one without its i-th vertex."""
+    F = canonical2(F)
+    edge_sets = [F[:, [1, 2]], F[:, [0, 2]], F[:, [0, 1]]]
+    E = np.unique(np.concatenate(edge_sets), axis=0)
+    ekey = {tuple(r): i for i, r in enumerate(E.tolist())}
+    tri_edges = np.array([[ekey[tuple(s[i])] for s in edge_sets] for i in range(len(F))],
+                         dtype=np.int64).reshape(-1, 3)
+    return E, tri_edges
+
+
+def certify2d(P: np.ndarray, F: np.ndarray) -> dict:
+    """Raises AssertionError unless F is the Delaunay triangulation of the
+    planar points P (Delaunay's lemma in the plane)."""
+    P = np.asarray(P, dtype=np.float64)
+    F = canonical2(F)
+    n = P.shape[0]
+    o, fb0 = orient2_sign(P[F[:, 0]], P[F[:, 1]], P[F[:, 2]])
+    assert np.all(o != 0), "degenerate triangle"
+    edge = np.concatenate([F[:, [1, 2]], F[:, [0, 2]], F[:, [0, 1]]])
+    opp = np.concatenate([F[:, 0], F[:, 1], F[:, 2]])
+    tri = np.concatenate([np.arange(len(F))] * 3)
+    key = np.lexsort(edge.T[::-1])
+    edge, opp, tri = edge[key], opp[key], tri[key]
+    same_next = np.all(edge[1:] == edge[:-1], axis=1)
+    assert not np.any(same_next[1:] & same_next[:-1]), "edge in more than two triangles"
+    first = np.flatnonzero(np.concatenate([[True], ~same_next]))
+    count = np.diff(np.concatenate([first, [len(edge)]]))
+    inner, hull = first[count == 2], first[count == 1]
+    e = edge[inner]
+    s1, fb1 = orient2_sign(P[e[:, 0]], P[e[:, 1]], P[opp[inner]])
+    s2, fb2 = orient2_sign(P[e[:, 0]], P[e[:, 1]], P[opp[inner + 1]])
+    assert np.all(s1 * s2 < 0), "triangles on the same side of a shared edge"
+    T1 = F[tri[inner]]
+    oo, _ = orient2_sign(P[T1[:, 0]], P[T1[:, 1]], P[T1[:, 2]])
+    si, fb3 = incircle_sign(P[T1[:, 0]], P[T1[:, 1]], P[T1[:, 2]], P[opp[inner + 1]])
+    assert np.all(si.astype(np.int64) * oo < 0), "not locally Delaunay (or cocircular)"
+    h = edge[hull]
+    side, _ = orient2_sign(P[h[:, 0]], P[h[:, 1]], P[opp[hull]])
+    member = np.zeros((len(h), n), dtype=bool)
+    member[np.arange(len(h))[:, None], h] = True
+    sgn, fbh = orient2_sign(P[h[:, 0]][:, None], P[h[:, 1]][:, None], P[None, :, :], skip=member)
+    bad = (sgn.astype(np.int64) * side.astype(np.int64)[:, None] < 0) | ((sgn == 0) & ~member)
+    assert not np.any(bad), "hull edge is not a supporting line"
+    assert len(np.unique(F)) == n, "point missing from the triangulation"
+    E, _ = faces2d(F)
+    assert n - len(E) + len(F) == 1, "Euler characteristic"
+    return {"triangles": len(F), "hull_edges": len(hull), "exact_fallbacks": fb0 + fb1 + fb2 + fb3 + fbh}
+
+
+def qhull_tris(P: np.ndarray) -> np.ndarray:
+    """scipy's qhull Delaunay in the plane, canonicalised."""
+    from scipy.spatial import Delaunay
+    return canonical2(Delaunay(np.asarray(P, dtype=np.float64)).simplices)

@@ -101,3 +101,65 @@ def insph_sign(a, b, c, d, e, skip=None):
     for ii in map(tuple, idx):
         s[ii] = insph_exact(a[ii], b[ii], c[ii], d[ii], e[ii])
     return s, len(idx)
+
+
+# --------------------------------------------------------------------------
+# the plane: orient2(a,b,c) = det[a-c; b-c] (positive for a counter-clockwise
+# a, b, c); incircle(a,b,c,d) = det of the 3x3 matrix with rows
+# (p - d, |p - d|^2), p in (a,b,c): d lies strictly inside the circle through
+# a counter-clockwise (a,b,c) iff it is positive
+
+
+def orient2_exact(a, b, c) -> int:
+    a, b, c = _fr(a), _fr(b), _fr(c)
+    v = (a[0] - c[0]) * (b[1] - c[1]) - (a[1] - c[1]) * (b[0] - c[0])
+    return (v > 0) - (v < 0)
+
+
+def incircle_exact(a, b, c, d) -> int:
+    d = _fr(d)
+    rows = []
+    for p in (a, b, c):
+        p = _fr(p)
+        r = [p[0] - d[0], p[1] - d[1]]
+        rows.append([r[0], r[1], r[0] * r[0] + r[1] * r[1]])
+    v = _det3_exact(*rows)
+    return (v > 0) - (v < 0)
+
+
+def orient2_sign(a, b, c, skip=None):
+    """Vectorised exact sign of orient2 on [..., 2] arrays; returns (int8
+    signs, exact fallbacks)."""
+    a, b, c = (np.asarray(x, dtype=np.float64) for x in (a, b, c))
+    a, b, c = np.broadcast_arrays(a, b, c)
+    A, B = a - c, b - c
+    det = A[..., 0] * B[..., 1] - A[..., 1] * B[..., 0]
+    perm = np.abs(A[..., 0] * B[..., 1]) + np.abs(A[..., 1] * B[..., 0])
+    s = np.asarray(np.sign(det), dtype=np.int8).copy()
+    unsure = np.abs(det) <= FILTER * perm
+    if skip is not None:
+        unsure &= ~skip
+    idx = np.argwhere(unsure)
+    for ii in map(tuple, idx):
+        s[ii] = orient2_exact(a[ii], b[ii], c[ii])
+    return s, len(idx)
+
+
+def incircle_sign(a, b, c, d, skip=None):
+    """Vectorised exact sign of incircle on [..., 2] arrays."""
+    a, b, c, d = (np.asarray(x, dtype=np.float64) for x in (a, b, c, d))
+    a, b, c, d = np.broadcast_arrays(a, b, c, d)
+    R = []
+    for p in (a, b, c):
+        r = p - d
+        R.append(np.concatenate([r, (r * r).sum(-1, keepdims=True)], axis=-1))
+    det = _det3(R[0], R[1], R[2])
+    perm = _perm3(R[0], R[1], R[2])
+    s = np.asarray(np.sign(det), dtype=np.int8).copy()
+    unsure = np.abs(det) <= FILTER * perm
+    if skip is not None:
+        unsure &= ~skip
+    idx = np.argwhere(unsure)
+    for ii in map(tuple, idx):
+        s[ii] = incircle_exact(a[ii], b[ii], c[ii], d[ii])
+    return s, len(idx)

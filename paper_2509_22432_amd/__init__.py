@@ -7,7 +7,7 @@ kernels (landmarks, grid, flooding, winners, backward) or its host code
 PyTorch provides device memory and the current HIP stream.
 """
 from .api import (  # noqa: F401
-    Complex, FloodFiltration, FloodProblem, delaunay, filtration, fps, fps_batched,
+    Complex, FloodFiltration, FloodProblem, delaunay, filtration, fps, fps_batched, lift_2d,
     n_interior, own_samples, persistence, problem_from_complexes,
 )
 from ._lib import FloodError  # noqa: F401

@@ -56,6 +56,8 @@ def lib():
     L.flood_fps.argtypes = [c_vp, c_i32, P(c_i64), c_vp, P(c_i32), c_vp, c_vp, c_vp, c_vp, c_vp, c_sz, c_vp]
     L.flood_delaunay.restype = c_i32
     L.flood_delaunay.argtypes = [c_vp, c_i32, P(c_vp)]
+    L.flood_delaunay2d.restype = c_i32
+    L.flood_delaunay2d.argtypes = [c_vp, c_i32, P(c_vp)]
     L.flood_complex_counts.restype = c_i32
     L.flood_complex_counts.argtypes = [c_vp, P(c_i64)]
     L.flood_complex_export.restype = c_i32
@@ -87,7 +89,7 @@ def check(status):
         raise FloodError(status, lib().flood_last_error().decode())
 
 
-EXPORTED = ["flood_last_error", "flood_fps_workspace_size", "flood_fps", "flood_delaunay",
+EXPORTED = ["flood_last_error", "flood_fps_workspace_size", "flood_fps", "flood_delaunay", "flood_delaunay2d",
             "flood_complex_counts", "flood_complex_export", "flood_complex_free",
             "flood_filtration_workspace_size", "flood_filtration", "flood_filtration_noalloc", "flood_filtration_backward",
             "flood_persistence", "flood_diagram_counts", "flood_diagram_export", "flood_diagram_free"]

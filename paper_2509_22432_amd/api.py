@@ -106,13 +106,16 @@ class Complex:
 
 
 def delaunay(Lxyz) -> Complex:
-    """Delaunay triangulation of landmark coordinates (host, exact predicates)."""
+    """Delaunay triangulation of landmark coordinates (host, exact
+    predicates): [L, 3] gives tetrahedra; [L, 2] (ambient dimension 2) gives
+    triangles, and the complex has no tetrahedra."""
     P = np.ascontiguousarray(np.asarray(Lxyz.detach().cpu() if torch.is_tensor(Lxyz) else Lxyz, dtype=np.float32))
-    if P.ndim != 2 or P.shape[1] != 3:
-        raise ValueError("Lxyz must be [L, 3]")
+    if P.ndim != 2 or P.shape[1] not in (2, 3):
+        raise ValueError("Lxyz must be [L, 3] or [L, 2]")
     L = lib()
     h = ctypes.c_void_p()
-    check(L.flood_delaunay(P.ctypes.data_as(ctypes.c_void_p), P.shape[0], ctypes.byref(h)))
+    call = L.flood_delaunay if P.shape[1] == 3 else L.flood_delaunay2d
+    check(call(P.ctypes.data_as(ctypes.c_void_p), P.shape[0], ctypes.byref(h)))
     try:
         cnt = (ctypes.c_int64 * 5)()
         check(L.flood_complex_counts(h, cnt))
@@ -126,6 +129,18 @@ def delaunay(Lxyz) -> Complex:
     finally:
         L.flood_complex_free(h)
     return Complex(P.shape[0], E, F, T, te, tt, int(cnt[4]))
+
+
+def lift_2d(P) -> np.ndarray:
+    """Planar coordinates [n, 2] as the library's [n, 3] rows with z = 0 (the
+    flooding kernels, the grid and the landmark rule then work in the plane:
+    every z difference is exactly 0)."""
+    P = np.asarray(P.detach().cpu() if torch.is_tensor(P) else P, dtype=np.float32)
+    if P.ndim != 2 or P.shape[1] != 2:
+        raise ValueError("expected [n, 2] coordinates")
+    out = np.zeros((P.shape[0], 3), np.float32)
+    out[:, :2] = P
+    return out
 
 
 def persistence(cx: Complex, f):

@@ -678,3 +678,374 @@ extern "C" flood_status flood_complex_export(const flood_complex *cx, int32_t *e
 }
 
 extern "C" void flood_complex_free(flood_complex *cx) { delete cx; }
+
+// ---------------------------------------------------------------------------
+// Delaunay triangulation in the plane (ambient dimension 2): the same
+// incremental construction with triangles, the orientation predicate
+// orient2(a,b,c) = det[a-c; b-c] and the in-circle predicate
+// incircle(a,b,c,d) = det of the rows (p - d, |p - d|^2), p in (a,b,c), which
+// is positive iff d lies strictly inside the circle through a positively
+// oriented (a,b,c).  FP64 filter, exact integer fallback.
+
+namespace {
+
+int orient2_exact(const float *a, const float *b, const float *c) {
+    const float A[3] = {a[0], a[1], 0.f}, B[3] = {b[0], b[1], 0.f}, C[3] = {c[0], c[1], 0.f};
+    const float *p[3] = {A, B, C};
+    ExactCoords x = exact_scale(p, 3);
+    Big u0 = x.c[0][0] - x.c[2][0], u1 = x.c[0][1] - x.c[2][1];
+    Big w0 = x.c[1][0] - x.c[2][0], w1 = x.c[1][1] - x.c[2][1];
+    return (u0 * w1 - u1 * w0).sign;
+}
+
+int incircle_exact(const float *a, const float *b, const float *c, const float *d) {
+    const float A[3] = {a[0], a[1], 0.f}, B[3] = {b[0], b[1], 0.f}, C[3] = {c[0], c[1], 0.f}, D[3] = {d[0], d[1], 0.f};
+    const float *p[4] = {A, B, C, D};
+    ExactCoords x = exact_scale(p, 4);
+    Big R[3][3];
+    for (int i = 0; i < 3; ++i) {
+        R[i][0] = x.c[i][0] - x.c[3][0];
+        R[i][1] = x.c[i][1] - x.c[3][1];
+        R[i][2] = R[i][0] * R[i][0] + R[i][1] * R[i][1];
+    }
+    return det3(R[0], R[1], R[2]).sign;
+}
+
+struct Predicates2 {
+    int64_t fallbacks = 0;
+    int orient(const float *a, const float *b, const float *c) {
+        const double ax = (double)a[0] - c[0], ay = (double)a[1] - c[1];
+        const double bx = (double)b[0] - c[0], by = (double)b[1] - c[1];
+        const double det = ax * by - ay * bx;
+        const double perm = std::fabs(ax * by) + std::fabs(ay * bx);
+        if (std::fabs(det) > 1e-13 * perm) return det > 0 ? 1 : -1;
+        ++fallbacks;
+        return orient2_exact(a, b, c);
+    }
+    int incircle(const float *a, const float *b, const float *c, const float *d) {
+        const float *p[3] = {a, b, c};
+        double R[3][3];
+        for (int i = 0; i < 3; ++i) {
+            R[i][0] = (double)p[i][0] - d[0];
+            R[i][1] = (double)p[i][1] - d[1];
+            R[i][2] = R[i][0] * R[i][0] + R[i][1] * R[i][1];
+        }
+        const double det = R[0][0] * (R[1][1] * R[2][2] - R[1][2] * R[2][1]) -
+                           R[0][1] * (R[1][0] * R[2][2] - R[1][2] * R[2][0]) +
+                           R[0][2] * (R[1][0] * R[2][1] - R[1][1] * R[2][0]);
+        const double perm = std::fabs(R[0][0]) * (std::fabs(R[1][1] * R[2][2]) + std::fabs(R[1][2] * R[2][1])) +
+                            std::fabs(R[0][1]) * (std::fabs(R[1][0] * R[2][2]) + std::fabs(R[1][2] * R[2][0])) +
+                            std::fabs(R[0][2]) * (std::fabs(R[1][0] * R[2][1]) + std::fabs(R[1][1] * R[2][0]));
+        if (std::fabs(det) > 1e-12 * perm) return det > 0 ? 1 : -1;
+        ++fallbacks;
+        return incircle_exact(a, b, c, d);
+    }
+};
+
+struct Tri {
+    int v[3];
+    int n[3];  // neighbour across the edge opposite v[i]
+};
+
+// triangles with an infinite vertex (-1) outside the hull; every triangle
+// positively oriented (for an infinite one: replacing the infinite vertex by a
+// point q gives a positive orientation iff q lies strictly beyond its hull edge)
+struct Triangulation2 {
+    const float *P;  // [L][2]
+    Predicates2 pr;
+    std::vector<Tri> t;
+    std::vector<char> dead;
+    std::vector<uint32_t> in_cav, tested;
+    std::vector<int> free_list, cavity, stack;
+    struct VertSlot {
+        int v, tri, edge;
+    };
+    std::vector<VertSlot> open_v;
+    uint32_t ins = 0;
+    int last = 0;
+    uint64_t rng = 0x2545f4914f6cdd1dull;
+
+    const float *pt(int i) const { return P + 2 * (size_t)i; }
+    static bool infinite_v(const Tri &x) { return x.v[0] == INF || x.v[1] == INF || x.v[2] == INF; }
+    bool infinite(int ti) const { return infinite_v(t[ti]); }
+    int new_tri() {
+        int i;
+        if (!free_list.empty()) {
+            i = free_list.back();
+            free_list.pop_back();
+        } else {
+            t.push_back(Tri{});
+            dead.push_back(0);
+            in_cav.push_back(0);
+            tested.push_back(0);
+            i = (int)t.size() - 1;
+        }
+        dead[i] = 0;
+        in_cav[i] = 0;
+        tested[i] = 0;
+        return i;
+    }
+    uint32_t rnd() {
+        rng ^= rng << 13;
+        rng ^= rng >> 7;
+        rng ^= rng << 17;
+        return (uint32_t)rng;
+    }
+    int orient_with(int ti, int i, int q) {
+        const Tri &x = t[ti];
+        const float *p[3];
+        for (int k = 0; k < 3; ++k) p[k] = (k == i) ? pt(q) : pt(x.v[k]);
+        return pr.orient(p[0], p[1], p[2]);
+    }
+    bool conflict(int ti, int q) {
+        const Tri &x = t[ti];
+        for (int k = 0; k < 3; ++k)
+            if (x.v[k] == INF) {
+                int o = orient_with(ti, k, q);
+                if (o == 0) throw Degenerate();
+                return o > 0;
+            }
+        int s = pr.incircle(pt(x.v[0]), pt(x.v[1]), pt(x.v[2]), pt(q));
+        if (s == 0) throw Degenerate();
+        return s > 0;
+    }
+    int locate(int q) {
+        int cur = last;
+        size_t steps = 0, limit = 8 * t.size() + 64;
+        while (steps++ < limit) {
+            if (infinite(cur)) return cur;
+            int start = (int)(rnd() % 3u);
+            int moved = -1;
+            for (int r = 0; r < 3; ++r) {
+                int i = (start + r) % 3;
+                if (orient_with(cur, i, q) < 0) {
+                    moved = t[cur].n[i];
+                    break;
+                }
+            }
+            if (moved < 0) return cur;
+            cur = moved;
+        }
+        for (int i = 0; i < (int)t.size(); ++i)
+            if (!dead[i] && conflict(i, q)) return i;
+        throw Degenerate();
+    }
+    void insert(int q) {
+        int c0 = locate(q);
+        if (!conflict(c0, q)) throw Degenerate();
+        ++ins;
+        cavity.clear();
+        stack.clear();
+        stack.push_back(c0);
+        in_cav[c0] = ins;
+        tested[c0] = ins;
+        while (!stack.empty()) {
+            int c = stack.back();
+            stack.pop_back();
+            cavity.push_back(c);
+            for (int i = 0; i < 3; ++i) {
+                int nb = t[c].n[i];
+                if (tested[nb] == ins) continue;
+                tested[nb] = ins;
+                if (conflict(nb, q)) {
+                    in_cav[nb] = ins;
+                    stack.push_back(nb);
+                }
+            }
+        }
+        // new triangles on the cavity boundary; the edges through q are glued
+        // by their other vertex (each boundary vertex meets two new triangles)
+        open_v.clear();
+        int created_finite = -1;
+        for (int c : cavity) {
+            for (int i = 0; i < 3; ++i) {
+                int nb = t[c].n[i];
+                if (in_cav[nb] == ins) continue;
+                Tri x = t[c];
+                x.v[i] = q;
+                for (int k = 0; k < 3; ++k) x.n[k] = -1;
+                x.n[i] = nb;
+                if (!infinite_v(x) && pr.orient(pt(x.v[0]), pt(x.v[1]), pt(x.v[2])) <= 0) throw Degenerate();
+                int nt = new_tri();
+                t[nt] = x;
+                for (int k = 0; k < 3; ++k)
+                    if (t[nb].n[k] == c) t[nb].n[k] = nt;
+                if (created_finite < 0 && !infinite_v(x)) created_finite = nt;
+                // the edge opposite slot j (j != i) joins q and the vertex in
+                // the third slot
+                for (int j = 0; j < 3; ++j) {
+                    if (j == i) continue;
+                    const int other = x.v[3 - i - j];
+                    size_t at = 0;
+                    while (at < open_v.size() && open_v[at].v != other) ++at;
+                    if (at == open_v.size()) {
+                        open_v.push_back(VertSlot{other, nt, j});
+                    } else {
+                        t[nt].n[j] = open_v[at].tri;
+                        t[open_v[at].tri].n[open_v[at].edge] = nt;
+                        open_v[at] = open_v.back();
+                        open_v.pop_back();
+                    }
+                }
+            }
+        }
+        if (!open_v.empty()) throw Degenerate();
+        for (int c : cavity) {
+            dead[c] = 1;
+            free_list.push_back(c);
+        }
+        if (created_finite >= 0) last = created_finite;
+    }
+};
+
+}  // namespace
+
+extern "C" flood_status flood_delaunay2d(const float *Lxy, int32_t L, flood_complex **out) {
+    using flood_host::set_error;
+    if (!out) {
+        set_error("flood_delaunay2d: out is NULL");
+        return FLOOD_EINVAL;
+    }
+    *out = nullptr;
+    if (!Lxy || L < 0) {
+        set_error("flood_delaunay2d: bad arguments");
+        return FLOOD_EINVAL;
+    }
+    if (L < 3) {
+        set_error("flood_delaunay2d: need at least 3 landmarks");
+        return FLOOD_EDEGENERATE;
+    }
+    for (int64_t i = 0; i < 2 * (int64_t)L; ++i)
+        if (!std::isfinite(Lxy[i])) {
+            set_error("flood_delaunay2d: non-finite coordinate");
+            return FLOOD_EINVAL;
+        }
+    try {
+        std::vector<int32_t> ord(L);
+        for (int32_t i = 0; i < L; ++i) ord[i] = i;
+        std::sort(ord.begin(), ord.end(), [&](int32_t a, int32_t b) {
+            return std::lexicographical_compare(Lxy + 2 * (size_t)a, Lxy + 2 * (size_t)a + 2, Lxy + 2 * (size_t)b,
+                                                Lxy + 2 * (size_t)b + 2);
+        });
+        for (int32_t i = 1; i < L; ++i)
+            if (std::memcmp(Lxy + 2 * (size_t)ord[i], Lxy + 2 * (size_t)ord[i - 1], 2 * sizeof(float)) == 0) {
+                set_error("flood_delaunay2d: duplicate landmark coordinates");
+                return FLOOD_EDEGENERATE;
+            }
+        // Morton insertion order
+        float lo[2] = {Lxy[0], Lxy[1]}, hi[2] = {Lxy[0], Lxy[1]};
+        for (int32_t i = 0; i < L; ++i)
+            for (int a = 0; a < 2; ++a) {
+                lo[a] = std::min(lo[a], Lxy[2 * (size_t)i + a]);
+                hi[a] = std::max(hi[a], Lxy[2 * (size_t)i + a]);
+            }
+        std::vector<std::pair<uint64_t, int32_t>> mk(L);
+        for (int32_t i = 0; i < L; ++i) {
+            uint64_t code = 0;
+            for (int a = 0; a < 2; ++a) {
+                double ext = (double)hi[a] - lo[a];
+                double u = ext > 0 ? ((double)Lxy[2 * (size_t)i + a] - lo[a]) / ext : 0.0;
+                uint64_t qv = (uint64_t)std::min(4294967295.0, std::max(0.0, u * 4294967295.0));
+                for (int bit = 0; bit < 32; ++bit) code |= ((qv >> bit) & 1ull) << (2 * bit + a);
+            }
+            mk[i] = {code, i};
+        }
+        std::sort(mk.begin(), mk.end());
+        Triangulation2 tr;
+        tr.P = Lxy;
+        std::vector<int32_t> seq(L);
+        for (int32_t i = 0; i < L; ++i) seq[i] = mk[i].second;
+        // first triangle: three points in insertion order that are not collinear
+        int32_t a0 = seq[0], a1 = seq[1], a2 = -1;
+        size_t ia2 = 0;
+        for (size_t i = 2; i < seq.size(); ++i)
+            if (tr.pr.orient(Lxy + 2 * (size_t)a0, Lxy + 2 * (size_t)a1, Lxy + 2 * (size_t)seq[i]) != 0) {
+                a2 = seq[i];
+                ia2 = i;
+                break;
+            }
+        if (a2 < 0) {
+            set_error("flood_delaunay2d: all landmarks are collinear");
+            return FLOOD_EDEGENERATE;
+        }
+        if (tr.pr.orient(Lxy + 2 * (size_t)a0, Lxy + 2 * (size_t)a1, Lxy + 2 * (size_t)a2) < 0) std::swap(a0, a1);
+        // triangle 0 finite; triangles 1..3 infinite, triangle 1 + i on the hull
+        // edge opposite vertex i of triangle 0 (its two vertices swapped)
+        tr.t.resize(4);
+        tr.dead.assign(4, 0);
+        tr.in_cav.assign(4, 0);
+        tr.tested.assign(4, 0);
+        const int vs[3] = {a0, a1, a2};
+        for (int i = 0; i < 3; ++i) {
+            tr.t[0].v[i] = vs[i];
+            tr.t[0].n[i] = 1 + i;
+        }
+        for (int i = 0; i < 3; ++i) {
+            // edge opposite vertex i: (vs[i+1], vs[i+2]) in the triangle's
+            // order; the infinite triangle takes it reversed
+            const int p = vs[(i + 1) % 3], q = vs[(i + 2) % 3];
+            Tri x;
+            x.v[0] = INF;
+            x.v[1] = q;
+            x.v[2] = p;
+            x.n[0] = 0;  // across the finite edge
+            // across the edge opposite q (INF, p): the infinite triangle on the
+            // hull edge that contains p and the third vertex, i.e. opposite q
+            int iq = 0, ip = 0;
+            for (int m = 0; m < 3; ++m) {
+                if (vs[m] == q) iq = m;
+                if (vs[m] == p) ip = m;
+            }
+            x.n[1] = 1 + iq;
+            x.n[2] = 1 + ip;
+            tr.t[1 + i] = x;
+        }
+        tr.last = 0;
+        for (size_t i = 0; i < seq.size(); ++i) {
+            if (i == 0 || i == 1 || i == ia2) continue;
+            tr.insert(seq[i]);
+        }
+        flood_complex *cx = new flood_complex();
+        cx->L = L;
+        cx->fallbacks = tr.pr.fallbacks;
+        for (size_t i = 0; i < tr.t.size(); ++i) {
+            if (tr.dead[i] || tr.infinite((int)i)) continue;
+            std::array<int32_t, 3> r = {tr.t[i].v[0], tr.t[i].v[1], tr.t[i].v[2]};
+            std::sort(r.begin(), r.end());
+            cx->F.push_back(r);
+        }
+        std::sort(cx->F.begin(), cx->F.end());
+        std::vector<std::array<int32_t, 4>> rec;  // (a, b, triangle row, slot)
+        rec.reserve(cx->F.size() * 3);
+        for (size_t j = 0; j < cx->F.size(); ++j) {
+            const auto &f = cx->F[j];
+            rec.push_back({f[1], f[2], (int32_t)j, 0});
+            rec.push_back({f[0], f[2], (int32_t)j, 1});
+            rec.push_back({f[0], f[1], (int32_t)j, 2});
+        }
+        std::sort(rec.begin(), rec.end());
+        cx->tri_edges.resize(cx->F.size());
+        for (size_t i = 0; i < rec.size(); ++i) {
+            if (i == 0 || rec[i][0] != rec[i - 1][0] || rec[i][1] != rec[i - 1][1]) cx->E.push_back({rec[i][0], rec[i][1]});
+            cx->tri_edges[rec[i][2]][rec[i][3]] = (int32_t)cx->E.size() - 1;
+        }
+        const int64_t euler = (int64_t)L - (int64_t)cx->E.size() + (int64_t)cx->F.size();
+        std::vector<char> used(L, 0);
+        for (auto &r : cx->F)
+            for (int k = 0; k < 3; ++k) used[r[k]] = 1;
+        const bool all_used = std::all_of(used.begin(), used.end(), [](char c) { return c != 0; });
+        if (euler != 1 || !all_used) {
+            delete cx;
+            set_error("flood_delaunay2d: internal consistency check failed (Euler characteristic or unused landmark)");
+            return FLOOD_EDEGENERATE;
+        }
+        *out = cx;
+        return FLOOD_OK;
+    } catch (Degenerate &) {
+        set_error("flood_delaunay2d: exactly degenerate configuration (collinear or cocircular points)");
+        return FLOOD_EDEGENERATE;
+    } catch (std::bad_alloc &) {
+        set_error("flood_delaunay2d: out of host memory");
+        return FLOOD_ENOMEM;
+    }
+}

@@ -702,6 +702,7 @@ __global__ __launch_bounds__(kWaveBlock) __attribute__((amdgpu_waves_per_eu(8, 8
     if (stats && blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(&stats[4 * a.d + 1], (unsigned long long)n);
     unsigned long long nev = 0;
     uint32_t nsteps = 0;  // ring steps (64 rows each) of this wave
+    uint32_t wmax_steps = 0, wlong = 0;  // its longest search; its searches of more than 32 steps
     // workgroups are dispatched to the 8 XCDs round-robin; each XCD takes the
     // queue segments x, x+8, ... through its own counter, so neighbouring
     // samples (same tile, same grid rows) meet in one L2
@@ -740,8 +741,11 @@ __global__ __launch_bounds__(kWaveBlock) __attribute__((amdgpu_waves_per_eu(8, 8
             const int64_t j = gid / (uint32_t)a.n_int;
             const int q = (int)(gid % (uint32_t)a.n_int);
             int32_t bi = 0x7fffffff;
+            const uint32_t steps0 = nsteps;
             const bool retired = ring_search<false>(g, cs, occ, xs, sx, sy, sz, bd, bi, a.d > 0, M, &key[j],
                                                     s_p0[wid], s_end[wid], lane, nev, nsteps);
+            wmax_steps = max(wmax_steps, nsteps - steps0);
+            wlong += nsteps - steps0 > 32 ? 1u : 0u;
             if (!retired && lane == 0) publish(key, seed, (int32_t)j, q, bd, a.d == 0, a.sampling == FLOOD_SAMPLING_RANDOM);
         }
     }
@@ -750,6 +754,8 @@ __global__ __launch_bounds__(kWaveBlock) __attribute__((amdgpu_waves_per_eu(8, 8
     if (evals && lane == 0 && nev) atomicAdd(evals, nev);
     if (stats && lane == 0 && nev) atomicAdd(&stats[4 * a.d + 3], nev);
     if (stats && lane == 0 && nsteps) atomicAdd(&stats[4 * a.d], (unsigned long long)nsteps);
+    if (stats && lane == 0 && wmax_steps) atomicMax(&stats[16 + 4 * a.d + 1], (unsigned long long)wmax_steps);
+    if (stats && lane == 0 && wlong) atomicAdd(&stats[16 + 4 * a.d + 2], (unsigned long long)wlong);
 }
 
 // x* of the winning own sample of every simplex (one wave per simplex): the

@@ -14,5 +14,5 @@ surfaces placed in the unit cube, plus isotropic Gaussian noise.
 from .clouds import (  # noqa: F401
     sphere_surface, torus_surface, box_surface, random_rotation,
     primitive_mix, config_cloud, batched_clouds, differentiable_clouds,
-    circle_points, lattice_points, swisscheese, CONFIGS,
+    circle_points, lattice_points, swisscheese, planar_cheese, CONFIGS,
 )

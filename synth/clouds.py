@@ -228,3 +228,27 @@ def swisscheese(n_points: int = 1_000_000, n_voids: int = 10, seed: int = 2000, 
         have += len(p)
     X = np.concatenate(out)[:n_points]
     return np.ascontiguousarray(X, dtype=np.float32), C, R
+
+
+def planar_cheese(n_points: int = 100_000, n_voids: int = 10, seed: int = 2100, side: float = 5.0):
+    """The swiss-cheese recipe in the plane (ambient dimension 2): points
+    uniform in [0, side]^2 minus n_voids disjoint disks with radii uniform in
+    [0.1, 0.5].  Returns float32 [n_points, 2]."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    cs, rs = [], []
+    while len(cs) < n_voids:
+        r = rng.uniform(0.1, 0.5)
+        c = rng.uniform(r, side - r, 2)
+        if all(np.linalg.norm(c - c2) > r + r2 for c2, r2 in zip(cs, rs)):
+            cs.append(c)
+            rs.append(r)
+    out, have = [], 0
+    while have < n_points:
+        m = int((n_points - have) * 1.1) + 64
+        p = rng.random((m, 2)) * side
+        keep = np.ones(m, dtype=bool)
+        for c, r in zip(cs, rs):
+            keep &= ((p - c) ** 2).sum(1) > r * r
+        out.append(p[keep])
+        have += int(keep.sum())
+    return np.ascontiguousarray(np.concatenate(out)[:n_points], dtype=np.float32)

@@ -18,7 +18,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 def test_exports_every_declared_symbol():
     hdr = open(os.path.join(ROOT, "include", "flood.h")).read()
-    names = set(re.findall(r"\b(flood_[a-z_]+)\s*\(", hdr))
+    names = set(re.findall(r"\b(flood_[a-z0-9_]+)\s*\(", hdr))
     assert names == set(_lib.EXPORTED)
     L = _lib.lib()
     for n in names:
@@ -191,3 +191,34 @@ def test_sampling_mode_validation():
     st = L.flood_filtration_backward(ctypes.byref(pb), ctypes.byref(out), g, ctypes.c_void_p(0x5000),
                                      ctypes.c_void_p(0x6000), None)
     assert st == _lib.EINVAL and "win_w" in L.flood_last_error().decode()
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_planar_delaunay_equals_brute_force_and_qhull(seed):
+    rng = np.random.default_rng(400 + seed)
+    Lx = rng.random((15 + 5 * seed, 2)).astype(np.float32)
+    cx = P.delaunay(Lx)
+    assert cx.T.shape == (0, 4) and cx.tet_tris.shape == (0, 4)
+    assert np.array_equal(cx.F, OD.brute_tris(Lx))
+    big = rng.random((3000, 2)).astype(np.float32)
+    cb = P.delaunay(big)
+    OD.certify2d(big, cb.F)
+    assert np.array_equal(cb.F, OD.qhull_tris(big))
+    E, te = OD.faces2d(cb.F)
+    assert np.array_equal(cb.E, E) and np.array_equal(cb.tri_edges, te)
+
+
+def test_planar_delaunay_errors_and_lift():
+    with pytest.raises(P.FloodError) as e:
+        P.delaunay(np.array([[0, 0], [1, 1], [2, 2], [3, 3]], np.float32))
+    assert e.value.status == _lib.EDEGENERATE
+    with pytest.raises(P.FloodError) as e:
+        P.delaunay(np.array([[0, 0], [1, 0], [1, 1], [0, 1]], np.float32))  # cocircular square
+    assert e.value.status == _lib.EDEGENERATE
+    pts = np.random.default_rng(1).random((9, 2)).astype(np.float32)
+    pts[4] = pts[7]
+    with pytest.raises(P.FloodError) as e:
+        P.delaunay(pts)
+    assert e.value.status == _lib.EDEGENERATE
+    lifted = P.lift_2d(np.ones((4, 2)))
+    assert lifted.shape == (4, 3) and np.all(lifted[:, 2] == 0) and lifted.dtype == np.float32

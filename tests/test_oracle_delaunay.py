@@ -90,3 +90,53 @@ def test_degenerate_rejected():
     cube = np.array([[x, y, z] for x in (0, 1) for y in (0, 1) for z in (0, 1)], np.float32)
     with pytest.raises(D.DegenerateInput):
         D.brute_tets(cube)
+
+
+# ---------------------------------------------------------------- the plane
+
+@pytest.mark.parametrize("seed", range(4))
+def test_planar_brute_equals_qhull_and_certificate(seed):
+    rng = np.random.default_rng(70 + seed)
+    P = rng.random((12 + 6 * seed, 2)).astype(np.float32)
+    F = D.brute_tris(P)
+    assert np.array_equal(F, D.qhull_tris(P))
+    info = D.certify2d(P, F)
+    E, _ = D.faces2d(F)
+    assert len(P) - len(E) + len(F) == 1 and info["triangles"] == len(F)
+
+
+def test_planar_certificate_rejects_a_flipped_edge_and_a_missing_triangle():
+    rng = np.random.default_rng(5)
+    P = rng.random((25, 2)).astype(np.float32)
+    F = [tuple(r) for r in D.brute_tris(P).tolist()]
+    with pytest.raises(AssertionError):
+        D.certify2d(P, np.array(F[1:]))
+    for i in range(len(F)):
+        for j in range(i + 1, len(F)):
+            s = set(F[i]) & set(F[j])
+            if len(s) != 2:
+                continue
+            a, b = sorted(s)
+            c, d = (set(F[i]) - s).pop(), (set(F[j]) - s).pop()
+            # the other diagonal of a convex quadrilateral
+            G = [f for k, f in enumerate(F) if k not in (i, j)] + [tuple(sorted((a, c, d))), tuple(sorted((b, c, d)))]
+            with pytest.raises(AssertionError):
+                D.certify2d(P, np.array(G))
+            return
+    raise AssertionError("no shared edge found")
+
+
+def test_planar_exact_predicates_decide_near_cocircular_points():
+    # float32 points of a circle: every quadruple is nearly cocircular, so
+    # the filter gives way to exact rational arithmetic
+    OP = P
+    t = 2 * np.pi * np.arange(8) / 8
+    C = np.stack([np.cos(t), np.sin(t)], 1).astype(np.float32)
+    s, fb = OP.incircle_sign(C[0], C[2], C[4], C[1:])
+    assert fb > 0
+    for k in range(1, 8):
+        assert s[k - 1] == OP.incircle_exact(C[0], C[2], C[4], C[k])
+    # the centre is inside, a far point outside (counter-clockwise triple)
+    assert OP.incircle_exact([1, 0], [0, 1], [-1, 0], [0, 0]) == 1
+    assert OP.incircle_exact([1, 0], [0, 1], [-1, 0], [0, -2]) == -1
+    assert OP.orient2_exact([0, 0], [1, 0], [0, 1]) == 1
