@@ -218,6 +218,11 @@ def main_block(args, torch, P, synth):
     Ld = Xd[idx.long()].contiguous()
     tuning = json.loads(args.tuning) if args.tuning else None
     pb = P.problem_from_complexes(Xd, [0, len(X)], Ld, [0, len(Lxyz)], [cx], args.k, l_xidx=idx.clone())
+    tune_ms = {}
+    if tuning is None and not args.no_autotune:
+        from paper_2509_22432_amd import autotune
+        tuning, tune_ms = autotune.autotune(pb, use_cache=False)
+        print("bench: autotuned %s" % tuning, file=sys.stderr, flush=True)
     run = P.api.FloodRun(pb, tuning, count_evals=False)
     hev = HipEvents(14)
     for i in range(12):
@@ -305,6 +310,7 @@ def main_block(args, torch, P, synth):
                                % (len(X), args.n_landmarks, args.k),
                    "N": len(X), "L": args.n_landmarks, "k": args.k, "simplices": [V, E, F, T],
                    "tuning": tuning},
+        "autotune_ms": tune_ms,
         "simplices_per_s": nsimp / (ms * 1e-3),
         "evals_per_step": ev,
         "evals_counted_in": "a separate instrumented run (median of 3); the timed steps run without counters",

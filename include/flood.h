@@ -271,7 +271,11 @@ typedef struct {
  * skips the cooperative search, 2..64, default 24),
  * queue_grab (open samples a wave of the per-sample search takes from the
  * queue per atomic: 1, 2, 4 or 8; default 4 when a dimension hands more
- * than 2^19 samples to that search, else 2). */
+ * than 2^19 samples to that search, else 2),
+ * tile_lanes (samples per tile of the cooperative search with
+ * samples_per_lane 1: 64, 32 or 16; with fewer than 64 each sample is held
+ * by 64/tile_lanes lanes that split every staged pass, so a tile covers a
+ * smaller region; 0 selects the per-dimension default). */
 typedef struct {
     float cells_per_point;
     int32_t samples_per_lane;
@@ -279,6 +283,7 @@ typedef struct {
     int32_t tile_shells;
     int32_t tile_extent;
     int32_t queue_grab;
+    int32_t tile_lanes;
 } flood_tuning;
 
 size_t flood_filtration_workspace_size(const flood_problem *pb, const flood_tuning *tune);

@@ -33,7 +33,7 @@ class Outputs(ctypes.Structure):
 
 class Tuning(ctypes.Structure):
     _fields_ = [("cells_per_point", c_f32), ("samples_per_lane", c_i32), ("waves_per_block", c_i32),
-                ("tile_shells", c_i32), ("tile_extent", c_i32), ("queue_grab", c_i32)]
+                ("tile_shells", c_i32), ("tile_extent", c_i32), ("queue_grab", c_i32), ("tile_lanes", c_i32)]
 
 
 _lib = None

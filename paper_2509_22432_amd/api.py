@@ -306,6 +306,7 @@ def _tuning(tuning):
     t.tile_shells = int(tuning.get("tile_shells", 0))
     t.tile_extent = int(tuning.get("tile_extent", 0))
     t.queue_grab = int(tuning.get("queue_grab", 0))
+    t.tile_lanes = int(tuning.get("tile_lanes", 0))
     return t
 
 

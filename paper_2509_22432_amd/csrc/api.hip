@@ -45,6 +45,7 @@ flood_tuning default_tuning(const flood_tuning *t) {
     r.tile_shells = 6;
     r.tile_extent = 24;
     r.queue_grab = 0;
+    r.tile_lanes = 0;
     if (t) {
         if (t->cells_per_point != 0) r.cells_per_point = t->cells_per_point;
         if (t->samples_per_lane != 0) r.samples_per_lane = t->samples_per_lane;
@@ -52,6 +53,7 @@ flood_tuning default_tuning(const flood_tuning *t) {
         if (t->tile_shells != 0) r.tile_shells = t->tile_shells;
         if (t->tile_extent != 0) r.tile_extent = t->tile_extent;
         r.queue_grab = t->queue_grab;
+        r.tile_lanes = t->tile_lanes;
     }
     return r;
 }
@@ -67,6 +69,8 @@ flood_status check_tuning(const flood_tuning &t) {
     if (t.tile_extent < 2 || t.tile_extent > 64) return fail(FLOOD_EINVAL, "tuning: tile_extent outside [2, 64]");
     if (t.queue_grab != 0 && t.queue_grab != 1 && t.queue_grab != 2 && t.queue_grab != 4 && t.queue_grab != 8)
         return fail(FLOOD_EINVAL, "tuning: queue_grab must be 0, 1, 2, 4 or 8");
+    if (t.tile_lanes != 0 && t.tile_lanes != 16 && t.tile_lanes != 32 && t.tile_lanes != 64)
+        return fail(FLOOD_EINVAL, "tuning: tile_lanes must be 0, 16, 32 or 64");
     return FLOOD_OK;
 }
 

@@ -28,6 +28,7 @@
 namespace flood {
 
 static constexpr int kWaveBlock = 256;
+static constexpr int kTileLanesDefault[4] = {64, 64, 64, 64};  // samples per tile of the tile search, by dimension
 static constexpr uint32_t kFineMin = 8;  // shortest cell run the tile search tests against every sample
 static constexpr int kU = 4;  // points per lane per step in the per-sample search
 static constexpr int kStage = 128;  // points staged in LDS per pass of the tile search
@@ -151,6 +152,8 @@ struct TileArgs {
     int32_t sampling;
     int64_t n_tiles;
     uint64_t seed;
+    int32_t lanes;             // samples per tile (64, or with T = 1: 32 or 16, each held by 64/lanes lanes)
+    int32_t pad;
 };
 
 __device__ __forceinline__ float box_lb2(float sx, float sy, float sz, float bx0, float bx1, float by0, float by1,
@@ -203,7 +206,11 @@ __global__ __launch_bounds__(kWaveBlock) __attribute__((amdgpu_waves_per_eu(T ==
     const int64_t sbase = s_off[b];
     const int64_t S = (s_off[b + 1] - sbase) * (int64_t)a.n_int;
     const int64_t x_lo = x_off[b], x_hi = x_off[b + 1];
-    const int64_t ls0 = (wave - tile_off[b]) * 64 * T;
+    // a tile of a.lanes samples (T = 1; 64 T otherwise); with fewer than 64,
+    // lane l holds sample l mod a.lanes, a copy that scans its share of every
+    // staged pass from the start (see grp below)
+    const int tl = T == 1 ? a.lanes : 64;
+    const int64_t ls0 = (wave - tile_off[b]) * (int64_t)tl * T;
     const int d = a.d;
 
     float sx[T], sy[T], sz[T], best[T], M[T];
@@ -211,7 +218,7 @@ __global__ __launch_bounds__(kWaveBlock) __attribute__((amdgpu_waves_per_eu(T ==
     bool live[T];
 #pragma unroll
     for (int t = 0; t < T; ++t) {
-        const int64_t ls = ls0 + (int64_t)t * 64 + lane;
+        const int64_t ls = ls0 + (int64_t)t * 64 + (lane & (tl - 1));
         const bool valid = ls < S;
         sx[t] = sy[t] = sz[t] = 0.f;
         best[t] = 0.f;
@@ -244,6 +251,11 @@ __global__ __launch_bounds__(kWaveBlock) __attribute__((amdgpu_waves_per_eu(T ==
             M[t] = seed[j];
         }
         live[t] = valid && !(sqrt_rn(best[t]) < M[t]);
+        if (live[t] && best[t] == 0.f) {
+            // a sample on a point of X: its value 0 is exact (a vertex sample)
+            if (lane < tl) publish(key, seed, sj[t], sq[t], 0.f, d == 0, a.sampling == FLOOD_SAMPLING_RANDOM);
+            live[t] = false;
+        }
     }
     const float h = g.h, eps = g.eps;
     // initial box: the cells of the live samples
@@ -274,7 +286,7 @@ __global__ __launch_bounds__(kWaveBlock) __attribute__((amdgpu_waves_per_eu(T ==
     // lane only) lane l holds a copy of lane l mod grp's sample and scans its
     // share of every staged pass, and the copies' minima are combined after
     // each shell
-    int grp = 64;
+    int grp = tl;
     const bool any_live = hi[0] >= 0;
     const bool compact = any_live && hi[0] - lo[0] < a.max_extent && hi[1] - lo[1] < a.max_extent &&
                          hi[2] - lo[2] < a.max_extent && a.radius_budget >= 0;
@@ -680,14 +692,20 @@ __device__ __forceinline__ int find_cloud(const int64_t *__restrict__ s_off, int
     return lo_b;
 }
 
-static constexpr uint32_t kGrab = 4;    // queue entries a wave takes per atomic on long queues
-static constexpr uint32_t kGrabSmall = 2;  // for short queues (tail balance); long queues take kGrab (fewer atomics)
-static constexpr uint32_t kSeg = 2048;  // queue segment of one XCD (spatially adjacent open samples)
+static constexpr uint32_t kGrab = 4;       // queue entries a wave takes per atomic on long queues
+static constexpr uint32_t kGrabSmall = 1;  // on short queues (tail balance)
+// The queue is read through kQueues cursors, each on a 256-byte line of its
+// own: atomics on one line are serialised, so a single line shared by every
+// wave caps the rate at which waves can take work.  Cursor c takes the
+// segments c, c + kQueues, ... of kSeg entries (neighbouring open samples
+// come from one tile); workgroup b reads through cursor b mod kQueues.
+static constexpr uint32_t kQueues = 16;
+static constexpr uint32_t kCursorStride = 64;  // uint32 words between cursors
+static constexpr uint32_t kSeg = 16;
 
-// queue position of the v-th entry an XCD takes (segments x, x+8, ... of
-// kSeg entries; increases with v)
-__device__ __forceinline__ uint32_t seg_index(uint32_t v, uint32_t xcd) {
-    return ((v / kSeg) * 8u + xcd) * kSeg + v % kSeg;
+// queue position of the v-th entry taken through cursor c (increases with v)
+__device__ __forceinline__ uint32_t seg_index(uint32_t v, uint32_t c) {
+    return ((v / kSeg) * kQueues + c) * kSeg + v % kSeg;
 }
 
 __global__ __launch_bounds__(kWaveBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_flood_deep(
@@ -703,23 +721,20 @@ __global__ __launch_bounds__(kWaveBlock) __attribute__((amdgpu_waves_per_eu(8, 8
     unsigned long long nev = 0;
     uint32_t nsteps = 0;  // ring steps (64 rows each) of this wave
     uint32_t wmax_steps = 0, wlong = 0;  // its longest search; its searches of more than 32 steps
-    // workgroups are dispatched to the 8 XCDs round-robin; each XCD takes the
-    // queue segments x, x+8, ... through its own counter, so neighbouring
-    // samples (same tile, same grid rows) meet in one L2
-    const uint32_t xcd = blockIdx.x & 7u;
+    const uint32_t cur = blockIdx.x % kQueues;
     const uint32_t grab = a.grab ? a.grab : (n > (1u << 19) ? kGrab : kGrabSmall);
     while (true) {
         uint32_t v0 = 0;
-        if (lane == 0) v0 = atomicAdd(&queue_next[xcd], grab);
+        if (lane == 0) v0 = atomicAdd(&queue_next[cur * kCursorStride], grab);
         v0 = __builtin_amdgcn_readfirstlane(v0);
-        if (seg_index(v0, xcd) >= n) break;
+        if (seg_index(v0, cur) >= n) break;
         // lanes 0..grab-1 fetch the grabbed entries and their simplices'
         // running values together (a stale value only retires less)
         float4 qp = make_float4(0.f, 0.f, 0.f, 0.f);
         uint32_t qg = 0, qc = 0;
         float qm = 0.f;
         if (lane < (int)grab) {
-            const uint32_t i = seg_index(v0 + lane, xcd);
+            const uint32_t i = seg_index(v0 + lane, cur);
             if (i < n) {
                 const OpenSample o = queue[i];
                 qp = o.p;
@@ -730,7 +745,7 @@ __global__ __launch_bounds__(kWaveBlock) __attribute__((amdgpu_waves_per_eu(8, 8
             }
         }
         for (int u = 0; u < (int)grab; ++u) {
-            if (seg_index(v0 + u, xcd) >= n) break;
+            if (seg_index(v0 + u, cur) >= n) break;
             const float sx = __uint_as_float(__builtin_amdgcn_readlane(__float_as_uint(qp.x), u));
             const float sy = __uint_as_float(__builtin_amdgcn_readlane(__float_as_uint(qp.y), u));
             const float sz = __uint_as_float(__builtin_amdgcn_readlane(__float_as_uint(qp.z), u));
@@ -894,7 +909,7 @@ size_t flood_workspace(const flood_problem *pb, float alpha, FloodSizes *sz) {
     bytes += 2 * (sizeof(uint32_t) * (bkmax + 1) + 256); // bucket counts and cursors
     bytes += sizeof(uint32_t) * scan_tmp_elems(bkmax + 1) + 256;
     bytes += sizeof(int32_t) * (pb->B + 1) + sizeof(uint32_t) * (pb->B + 1) + 512;
-    bytes += sizeof(uint32_t) * 16 + 256;             // queue count and per-XCD cursors
+    bytes += sizeof(uint32_t) * kCursorStride * (kQueues + 1) + 256;  // queue count and cursors
     bytes += 4 * (sizeof(int64_t) * (pb->B + 1) + 256); // tile offsets
     bytes += 1024;
     if (sz) {
@@ -934,7 +949,8 @@ hipError_t flood_run(const flood_problem *pb, const flood_tuning &tu, const floo
     float *seed = c.take<float>(nmax + 1);
     uint64_t *key = c.take<uint64_t>(nmax + 1);
     OpenSample *hard = c.take<OpenSample>(smax + 1);
-    uint32_t *counters = c.take<uint32_t>(16);  // [0] open samples, [8..15] per-XCD queue cursors
+    // [0] open samples; the queue cursors from word kCursorStride on, kCursorStride apart
+    uint32_t *counters = c.take<uint32_t>(kCursorStride * (kQueues + 1));
     int64_t bkmax = 0;
     for (int d = 0; d < 4; ++d) {
         int64_t bk = 0;
@@ -960,6 +976,10 @@ hipError_t flood_run(const flood_problem *pb, const flood_tuning &tu, const floo
     if (out->grid_events[1] && (e = hipEventRecord((hipEvent_t)out->grid_events[1], s)) != hipSuccess) return e;
     const int T = tu.samples_per_lane;
     const int wpb = tu.waves_per_block;
+    // samples per tile by dimension (T = 1): one value from the tuning, or
+    // the defaults below
+    int tile_lanes[4];
+    for (int d = 0; d < 4; ++d) tile_lanes[d] = tu.tile_lanes ? tu.tile_lanes : kTileLanesDefault[d];
     for (int d = 0; d < 4; ++d) {
         const int64_t n = sz.n[d];
         if (n == 0) continue;
@@ -972,10 +992,10 @@ hipError_t flood_run(const flood_problem *pb, const flood_tuning &tu, const floo
                            pb->tri_edges, pb->tet_tris, d > 0 ? out->f[d - 1] : nullptr, seed);
         e = fill_u64(key, 0ull, n, s);
         if (e != hipSuccess) return e;
-        e = fill_u32(counters, 0u, 16, s);
+        e = fill_u32(counters, 0u, kCursorStride * (kQueues + 1), s);
         if (e != hipSuccess) return e;
         if (nint > 0) {
-            const int64_t tsamp = 64 * (int64_t)T;
+            const int64_t tsamp = (T == 1 ? (int64_t)tile_lanes[d] : 64) * (int64_t)T;
             int64_t ntiles = 0;
             for (int32_t b = 0; b < pb->B; ++b) ntiles += ((soff_h[b + 1] - soff_h[b]) * nint + tsamp - 1) / tsamp;
             hipLaunchKernelGGL(k_tile_off, dim3(1), dim3(1024), 0, s, soff_d, pb->B, nint, tsamp, tile_off[d]);
@@ -1006,6 +1026,8 @@ hipError_t flood_run(const flood_problem *pb, const flood_tuning &tu, const floo
                 ta.sampling = pb->sampling;
                 ta.n_tiles = ntiles;
                 ta.seed = pb->seed;
+                ta.lanes = T == 1 ? tile_lanes[d] : 64;
+                ta.pad = 0;
                 if (out->tile_events[3 * d]) {
                     e = hipEventRecord((hipEvent_t)out->tile_events[3 * d], s);
                     if (e != hipSuccess) return e;
@@ -1025,7 +1047,7 @@ hipError_t flood_run(const flood_problem *pb, const flood_tuning &tu, const floo
                 da.grab = (uint32_t)tu.queue_grab;
                 da.sampling = pb->sampling;
                 hipLaunchKernelGGL(k_flood_deep, dim3(2048), dim3(256), 0, s, da, seed, key,
-                                   g.gp, g.cell_start, g.occ, g.xs, hard, counters, counters + 8,
+                                   g.gp, g.cell_start, g.occ, g.xs, hard, counters, counters + kCursorStride,
                                    (unsigned long long *)out->evals, (unsigned long long *)out->stats);
                 if (out->tile_events[3 * d + 2]) {
                     e = hipEventRecord((hipEvent_t)out->tile_events[3 * d + 2], s);

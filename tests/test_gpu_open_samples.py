@@ -34,7 +34,8 @@ def test_hollow_sphere_open_samples():
         if len(ref[d][0]):
             err = float(np.abs(base["out"]["f"][d].astype(np.float64) - ref[d][0]).max())
             assert err <= 1e-5 * diam, (d, err, 1e-5 * diam)
-    for tu in ({"tile_shells": 1}, {"tile_shells": 3}, {"tile_shells": 12, "tile_extent": 64}):
+    for tu in ({"tile_shells": 1}, {"tile_shells": 3}, {"tile_shells": 12, "tile_extent": 64}, {"tile_lanes": 16},
+               {"tile_lanes": 32, "tile_shells": 1}):
         print("hollow sphere tuning", tu, flush=True)
         other = run_single(X, 48, k, tuning=tu)
         for d in range(4):

@@ -124,7 +124,8 @@ def test_tuning_invariance_and_determinism():
     for tu in ({"samples_per_lane": 2}, {"samples_per_lane": 4}, {"cells_per_point": 0.2},
                {"cells_per_point": 6.0, "waves_per_block": 1}, {"tile_shells": -1}, {"tile_shells": 1},
             {"tile_shells": 4, "samples_per_lane": 2}, {"tile_shells": 2}, {"tile_shells": 16},
-            {"tile_shells": 32, "tile_extent": 64}):
+            {"tile_shells": 32, "tile_extent": 64}, {"tile_lanes": 32}, {"tile_lanes": 16},
+            {"tile_lanes": 16, "tile_shells": 2}, {"tile_lanes": 64}, {"tile_lanes": 16, "samples_per_lane": 2}):
         other = run_single(X, 400, 6, tuning=tu)
         for d in range(4):
             assert np.array_equal(base["out"]["f"][d], other["out"]["f"][d]), (tu, d)

@@ -85,7 +85,8 @@ def test_random_winners_and_weights():
 def test_random_tuning_invariance_and_batched_equals_plain():
     X = synth.config_cloud(2, 100_000)
     base = run_single(X, 400, 24, sampling="random", seed=7)
-    for tu in ({"samples_per_lane": 2}, {"tile_shells": -1}, {"tile_shells": 2, "cells_per_point": 0.3}):
+    for tu in ({"samples_per_lane": 2}, {"tile_shells": -1}, {"tile_shells": 2, "cells_per_point": 0.3},
+               {"tile_lanes": 16}, {"tile_lanes": 32}):
         other = run_single(X, 400, 24, tuning=tu, sampling="random", seed=7)
         for d in range(4):
             for part in ("f", "win_x", "win_a", "win_w"):

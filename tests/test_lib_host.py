@@ -66,7 +66,8 @@ def test_filtration_rejects_small_workspace_and_bad_tuning():
     t = _lib.Tuning(1.0, 1, 5, 0, 0)
     assert L.flood_filtration(ctypes.byref(pb), ctypes.byref(t), ctypes.byref(out), None, 0, None) == _lib.EINVAL
     for bad in ((1.0, 1, 4, 33, 0), (1.0, 1, 4, -2, 0), (1.0, 1, 4, 0, 65), (1.0, 1, 4, 0, 1), (1.0, 1, 4, 0, 0, 3),
-                (1.0, 1, 4, 0, 0, 16), (1.0, 1, 4, 0, 0, -1)):
+                (1.0, 1, 4, 0, 0, 16), (1.0, 1, 4, 0, 0, -1), (1.0, 1, 4, 0, 0, 0, 8), (1.0, 1, 4, 0, 0, 0, 48),
+                (1.0, 1, 4, 0, 0, 0, -16)):
         t = _lib.Tuning(*bad)
         assert L.flood_filtration(ctypes.byref(pb), ctypes.byref(t), ctypes.byref(out), None, 0, None) == _lib.EINVAL
 
