@@ -271,7 +271,7 @@ typedef struct {
  * skips the cooperative search, 2..64, default 24),
  * queue_grab (open samples a wave of the per-sample search takes from the
  * queue per atomic: 1, 2, 4 or 8; default 4 when a dimension hands more
- * than 2^19 samples to that search, else 2),
+ * than 2^19 samples to that search, else 1),
  * tile_lanes (samples per tile of the cooperative search with
  * samples_per_lane 1: 64, 32 or 16; with fewer than 64 each sample is held
  * by 64/tile_lanes lanes that split every staged pass, so a tile covers a
