@@ -41,6 +41,7 @@ HBM_PEAK_GBS = 8000.0
 FLOP_PER_EVAL = 8  # 3 sub + 1 mul + 2 fma (2 each)
 GRID_BYTES_PER_POINT = 100  # bbox 12 + count 12 + partition 12 + 16 + bucket sort 16 + 16 + 16
 TOL = 1e-5  # |df| / diam(X)
+TRAFFIC_PATH = os.path.join(ROOT, "profiles", "traffic.json")
 
 
 def hip_runtime():
@@ -73,12 +74,13 @@ class HipEvents:
                 e.value = None
 
 
-def measured_traffic(kernel):
+def measured_traffic(kernel, tuning=None):
     """HBM bytes per launch of `kernel` from the committed counter summary
     (FETCH_SIZE and WRITE_SIZE passes scaled by a plain-copy calibration),
-    or None when the kernel's sources changed since the counters were taken."""
+    or None when the kernel's sources changed since the counters were taken
+    or the counters were taken at another tuning."""
     try:
-        t = json.load(open(os.path.join(ROOT, "profiles", "traffic.json")))
+        t = json.load(open(TRAFFIC_PATH))
         k = t["kernels"][kernel]
         m = hashlib.sha256()
         for f in k["sources"]:
@@ -87,7 +89,70 @@ def measured_traffic(kernel):
         return None
     if m.hexdigest() != k["sources_sha256"]:
         return None
+    if "tuning" in k and k["tuning"] != (tuning or {}):
+        return None
     return k["fetch_bytes_per_launch"] + k["write_bytes_per_launch"]
+
+
+# source files each profiled kernel is compiled from (the traffic figures
+# are dropped once any of them changes)
+TRAFFIC_SOURCES = {
+    "flood::k_flood_tiles<1>": ["flood.hip", "sample.hpp", "internal.hpp"],
+    "flood::k_flood_deep": ["flood.hip", "sample.hpp", "internal.hpp"],
+    "flood::k_winner_search": ["flood.hip", "sample.hpp", "internal.hpp"],
+    "flood::k_fps_coop<0>": ["fps.hip", "internal.hpp"],
+}
+
+
+def _counter_rows(d):
+    """(kernel name, dispatch id) -> counter value from one rocprofv3 --pmc
+    csv directory (one counter per pass)."""
+    import csv
+    import glob
+    out = {}
+    for f in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+        for r in csv.DictReader(open(f)):
+            name = r["Kernel_Name"].split("(")[0].replace("void ", "").strip()
+            key = (name, int(r["Dispatch_Id"]))
+            out[key] = out.get(key, 0.0) + float(r["Counter_Value"])
+    return out
+
+
+def write_traffic(pmc_dir, tuning):
+    """profiles/traffic.json from four rocprofv3 --pmc runs under pmc_dir:
+    pmc_fetch / pmc_write (FETCH_SIZE / WRITE_SIZE of the bench), and
+    pmc_copy_fetch / pmc_copy_write (the same counters for a plain copy of
+    known size, `--calibrate-copy`), which give the KiB-to-bytes scale."""
+    copy_bytes = 1 << 30
+    cal = {}
+    for c, sub in (("fetch", "pmc_copy_fetch"), ("write", "pmc_copy_write")):
+        rows = _counter_rows(os.path.join(pmc_dir, sub))
+        vals = [v for (n, _), v in rows.items() if "copy" in n.lower()]
+        cal[c] = copy_bytes / (float(np.median(vals)) * 1024.0)
+    kern = {}
+    for c, sub in (("fetch", "pmc_fetch"), ("write", "pmc_write")):
+        rows = _counter_rows(os.path.join(pmc_dir, sub))
+        for name in TRAFFIC_SOURCES:
+            vals = [v for (n, _), v in sorted(rows.items(), key=lambda kv: kv[0][1]) if n == name]
+            if vals:
+                kern.setdefault(name, {})[c] = (float(np.mean(vals)) * 1024.0 * cal[c], len(vals))
+    out = {"calibration": {"copy_bytes": copy_bytes, "fetch_scale": cal["fetch"], "write_scale": cal["write"]},
+           "kernels": {}}
+    for name, v in kern.items():
+        if "fetch" not in v or "write" not in v:
+            continue
+        m = hashlib.sha256()
+        for f in TRAFFIC_SOURCES[name]:
+            m.update(open(os.path.join(ROOT, "paper_2509_22432_amd", "csrc", f), "rb").read())
+        out["kernels"][name] = {"fetch_bytes_per_launch": v["fetch"][0], "write_bytes_per_launch": v["write"][0],
+                                "dispatches_averaged": v["fetch"][1],
+                                "sources": TRAFFIC_SOURCES[name], "sources_sha256": m.hexdigest()}
+        if "fps" not in name:  # the landmark kernel takes no tuning
+            out["kernels"][name]["tuning"] = tuning or {}
+    with open(TRAFFIC_PATH, "w") as f:
+        json.dump(out, f, indent=1, sort_keys=True)
+        f.write("\n")
+    print(json.dumps(out, indent=1, sort_keys=True))
 
 
 # ---------------------------------------------------------------------------
@@ -239,7 +304,8 @@ def main_block(args, torch, P, synth):
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
-    P.api.check_landmarks(last["idx"])
+    if "idx" in last:
+        P.api.check_landmarks(last["idx"])
     fps_ms, flood_ms, tile_ms, grid_ms = [], [], [], []
     t_start = torch.cuda.Event(enable_timing=True)
     t_end = torch.cuda.Event(enable_timing=True)
@@ -291,7 +357,7 @@ def main_block(args, torch, P, synth):
     n_unique = [V] + [pb.n(d) * P.n_interior(d, args.k) for d in (1, 2, 3)]
     g_ms = float(np.mean(grid_ms))
     fps_mean = float(np.mean(fps_ms))
-    traffic = measured_traffic("flood::" + dominant[0])
+    traffic = measured_traffic("flood::" + dominant[0], tuning)
     fps_traffic = measured_traffic("flood::k_fps_coop<0>")
     out = {
         "metric": METRIC,
@@ -426,12 +492,14 @@ def batched_block(args, reps):
         times.append(e0.elapsed_time(e1))
     g_ms = float(np.median(times))
     f = [t.cpu().numpy() for t in gf.run.f]
-    gf.run.evals.zero_()
-    gf.run.stats.zero_()
-    gf.replay()
+    # the counts from a separate instrumented call (the replays run without counters)
+    irun = api.FloodRun(pb, tuning, count_evals=True)
+    irun()
     torch.cuda.synchronize()
-    evals = int(gf.run.evals.item())
-    stats = gf.run.stats.view(8, 4).cpu().numpy()
+    evals = int(irun.evals.item())
+    stats = irun.stats.view(8, 4).cpu().numpy()
+    counted_equal = all(np.array_equal(irun.f[d].cpu().numpy(), f[d]) for d in range(4))
+    del irun
     # the same clouds as separate plain calls (one problem per cloud)
     singles = []
     for b in range(len(clouds)):
@@ -458,7 +526,7 @@ def batched_block(args, reps):
            "clouds_per_s": len(clouds) / (g_ms * 1e-3), "graph_replay_ms": g_ms,
            "plain_per_cloud_calls_ms": plain_ms, "plain_clouds_per_s": len(clouds) / (plain_ms * 1e-3),
            "tuning": tuning, "autotune_ms": timings,
-           "points": int(pb.x_off[-1]), "landmarks": V, "simplices": n_simp, "evals": evals,
+           "points": int(pb.x_off[-1]), "landmarks": V, "simplices": n_simp, "evals": evals, "evals_counted_in": "a separate instrumented call (bit-identical f: %s)" % counted_equal,
            "search_stats_per_dim": {"per_sample_search_samples": [int(v) for v in stats[:4, 1]],
                                     "tile_evals": [int(v) for v in stats[:4, 2]],
                                     "per_sample_evals": [int(v) for v in stats[:4, 3]]},
@@ -646,6 +714,9 @@ def main():
     ap.add_argument("--sweep", choices=["x", "l", "table", "all"], default=None)
     ap.add_argument("--sweep-k", type=int, default=29, help="segments per edge in the sweeps (30 points per edge)")
     ap.add_argument("--sweep-out", type=str, default="gpurun_out/sweep.json")
+    ap.add_argument("--write-traffic", type=str, default=None, metavar="PMC_DIR",
+                    help="write profiles/traffic.json from rocprofv3 FETCH_SIZE/WRITE_SIZE runs under PMC_DIR "
+                         "(pmc_fetch, pmc_write, pmc_copy_fetch, pmc_copy_write) taken at --tuning; no GPU")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device copy three times (scale for the FETCH_SIZE / "
                          "WRITE_SIZE counters) and exit")
@@ -655,6 +726,9 @@ def main():
               "(--gpus %d requested)" % args.gpus, file=sys.stderr)
         sys.exit(2)
 
+    if args.write_traffic:
+        write_traffic(args.write_traffic, json.loads(args.tuning) if args.tuning else None)
+        return
     import torch
     if args.calibrate_copy:
         n = 1 << 28

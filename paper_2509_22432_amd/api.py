@@ -368,7 +368,9 @@ class FloodRun:
 
 
 def filtration(pb: FloodProblem, tuning=None, count_evals=True):
-    """One forward call.  Returns the FloodRun holding f, win_x, win_a, evals."""
+    """One forward call.  Returns the FloodRun holding f, win_x, win_a, evals.
+    count_evals turns on the kernels' evaluation and search counters (per-wave
+    atomics: a diagnostic run; timed and production calls pass False)."""
     run = FloodRun(pb, tuning, count_evals)
     run()
     return run

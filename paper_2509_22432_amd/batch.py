@@ -37,10 +37,12 @@ def prepare(clouds, n_lm, k, threads=16, sampling="grid", seed=0):
 
 
 class GraphedFiltration:
-    """The whole batched filtration captured once and replayed."""
+    """The whole batched filtration captured once and replayed (with
+    count_evals, the debug counters are captured too; they add per-wave
+    atomics, so timed replays leave them out)."""
 
-    def __init__(self, pb, tuning=None):
-        self.run = api.FloodRun(pb, tuning, count_evals=True)
+    def __init__(self, pb, tuning=None, count_evals=False):
+        self.run = api.FloodRun(pb, tuning, count_evals=count_evals)
         self.run()  # warm-up outside capture
         torch.cuda.synchronize()
         self.graph = torch.cuda.CUDAGraph()
