@@ -37,8 +37,12 @@ static constexpr int kStage = 128;  // points staged in LDS per pass of the tile
 // bound, its id (simplex * interior samples + rank) and cloud
 struct __align__(16) OpenSample {
     float4 p;  // x, y, z, squared-distance bound
-    uint32_t gid, cloud, pad0, pad1;
+    uint32_t gid, cloud;
+    // after the per-sample search: the nearest point's row and the value
+    // (float bits) when the search ran to the end, kNoRow otherwise
+    uint32_t xrow, val;
 };
+static constexpr uint32_t kNoRow = 0xffffffffu;
 
 // ---------------------------------------------------------------------------
 // per-dimension helpers
@@ -529,7 +533,8 @@ __global__ __launch_bounds__(kWaveBlock) __attribute__((amdgpu_waves_per_eu(T ==
             o.p = make_float4(sx[t], sy[t], sz[t], best[t]);
             o.gid = (uint32_t)(sj[t] * (int64_t)a.n_int + sq[t]);
             o.cloud = (uint32_t)b;
-            o.pad0 = o.pad1 = 0u;
+            o.xrow = kNoRow;
+            o.val = 0u;
             hard[slot] = o;
         }
     }
@@ -711,7 +716,7 @@ __device__ __forceinline__ uint32_t seg_index(uint32_t v, uint32_t c) {
 __global__ __launch_bounds__(kWaveBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_flood_deep(
     DeepArgs a, const float *__restrict__ seed, uint64_t *__restrict__ key, const GridParam *__restrict__ gp,
     const uint32_t *__restrict__ cs, const uint32_t *__restrict__ occ, const float4 *__restrict__ xs,
-    const OpenSample *__restrict__ queue,
+    OpenSample *__restrict__ queue,
     const uint32_t *__restrict__ queue_count, uint32_t *__restrict__ queue_next,
     unsigned long long *__restrict__ evals, unsigned long long *__restrict__ stats) {
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
@@ -757,11 +762,19 @@ __global__ __launch_bounds__(kWaveBlock) __attribute__((amdgpu_waves_per_eu(8, 8
             const int q = (int)(gid % (uint32_t)a.n_int);
             int32_t bi = 0x7fffffff;
             const uint32_t steps0 = nsteps;
-            const bool retired = ring_search<false>(g, cs, occ, xs, sx, sy, sz, bd, bi, a.d > 0, M, &key[j],
-                                                    s_p0[wid], s_end[wid], lane, nev, nsteps);
+            // the point row is kept as well: when this sample wins, its x*
+            // is this search's (the same lexicographic minimum the winner
+            // search would find), and that search is skipped
+            const bool retired = ring_search<true>(g, cs, occ, xs, sx, sy, sz, bd, bi, a.d > 0, M, &key[j],
+                                                   s_p0[wid], s_end[wid], lane, nev, nsteps);
             wmax_steps = max(wmax_steps, nsteps - steps0);
             wlong += nsteps - steps0 > 32 ? 1u : 0u;
-            if (!retired && lane == 0) publish(key, seed, (int32_t)j, q, bd, a.d == 0, a.sampling == FLOOD_SAMPLING_RANDOM);
+            if (lane == 0) {
+                const uint32_t i = seg_index(v0 + u, cur);
+                if (!retired) publish(key, seed, (int32_t)j, q, bd, a.d == 0, a.sampling == FLOOD_SAMPLING_RANDOM);
+                queue[i].xrow = retired || bi == 0x7fffffff ? kNoRow : (uint32_t)bi;
+                queue[i].val = __float_as_uint(sqrt_rn(bd));
+            }
         }
     }
 #pragma unroll
@@ -771,6 +784,24 @@ __global__ __launch_bounds__(kWaveBlock) __attribute__((amdgpu_waves_per_eu(8, 8
     if (stats && lane == 0 && nsteps) atomicAdd(&stats[4 * a.d], (unsigned long long)nsteps);
     if (stats && lane == 0 && wmax_steps) atomicMax(&stats[16 + 4 * a.d + 1], (unsigned long long)wmax_steps);
     if (stats && lane == 0 && wlong) atomicAdd(&stats[16 + 4 * a.d + 2], (unsigned long long)wlong);
+}
+
+// winners whose sample the per-sample search completed: x* is that search's
+// nearest point; the key is cleared so the winner search skips the simplex
+// (after k_winner, which reads the key)
+__global__ __launch_bounds__(256) void k_match_winners(const OpenSample *__restrict__ queue,
+                                                       const uint32_t *__restrict__ queue_count, int32_t n_int,
+                                                       uint64_t *__restrict__ key, int32_t *__restrict__ win_x) {
+    const uint32_t n = *queue_count;
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        const OpenSample o = queue[i];
+        if (o.xrow == kNoRow) continue;
+        const uint32_t j = o.gid / (uint32_t)n_int, q = o.gid % (uint32_t)n_int;
+        if (key[j] == (((uint64_t)o.val << 32) | (uint64_t)(0xffffffffu - q))) {
+            win_x[j] = (int32_t)o.xrow;
+            key[j] = 0;
+        }
+    }
 }
 
 // x* of the winning own sample of every simplex (one wave per simplex): the
@@ -994,10 +1025,12 @@ hipError_t flood_run(const flood_problem *pb, const flood_tuning &tu, const floo
         if (e != hipSuccess) return e;
         e = fill_u32(counters, 0u, kCursorStride * (kQueues + 1), s);
         if (e != hipSuccess) return e;
+        int64_t ntiles_d = 0;  // tiles of this dimension (0: no search ran)
         if (nint > 0) {
             const int64_t tsamp = (T == 1 ? (int64_t)tile_lanes[d] : 64) * (int64_t)T;
             int64_t ntiles = 0;
             for (int32_t b = 0; b < pb->B; ++b) ntiles += ((soff_h[b + 1] - soff_h[b]) * nint + tsamp - 1) / tsamp;
+            ntiles_d = ntiles;
             hipLaunchKernelGGL(k_tile_off, dim3(1), dim3(1024), 0, s, soff_d, pb->B, nint, tsamp, tile_off[d]);
             // spatial order of the samples
             int64_t bk = 0;
@@ -1060,6 +1093,9 @@ hipError_t flood_run(const flood_problem *pb, const flood_tuning &tu, const floo
                            d > 0 ? out->win_x[d - 1] : nullptr, d > 0 ? out->win_a[d - 1] : nullptr,
                            d > 0 ? out->win_w[d - 1] : nullptr, out->f[d], out->win_x[d], out->win_a[d],
                            out->win_w[d]);
+        if (nint > 0 && ntiles_d > 0)
+            hipLaunchKernelGGL(k_match_winners, dim3(1024), dim3(256), 0, s, hard, counters, (int32_t)nint, key,
+                               out->win_x[d]);
         hipLaunchKernelGGL(k_winner_search, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, s, d, rule, n, pb->B,
                            pb->Lxyz, simp, soff_d, key, g.gp, g.cell_start, g.occ, g.xs, out->win_x[d]);
         e = hipGetLastError();
