@@ -351,6 +351,38 @@ __global__ __launch_bounds__(kWaveBlock) __attribute__((amdgpu_waves_per_eu(T ==
                     // (a run shorter than kFineMin points is kept: testing it costs more
                     // than scanning it)
                     uint64_t mask = __ballot(ok && p1 - p0 >= kFineMin), need_m = __ballot(ok && p1 - p0 < kFineMin);
+                    if (T == 1 && grp < 64 && mask) {
+                        // every group of grp lanes holds each of the tile's
+                        // samples once, so the groups test 64 / grp runs at
+                        // a time: group c takes run c of the round
+                        const int nm = __popcll(mask);
+                        const int lg = __builtin_ctz((unsigned)grp);
+                        if ((mask >> lane) & 1ull) sw_p0[__popcll(mask & ((1ull << lane) - 1ull))] = (uint32_t)lane;
+                        sw_end[lane] = 0u;
+                        __builtin_amdgcn_wave_barrier();
+                        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                        for (int r0 = 0; r0 < nm; r0 += 64 >> lg) {
+                            const int idx = r0 + (lane >> lg);
+                            const int src = idx < nm ? (int)sw_p0[idx] : 0;
+                            const int rx0 = __shfl(x0, src, 64), rx1 = __shfl(x1, src, 64);
+                            const int ry = __shfl(y, src, 64), rz = __shfl(z, src, 64);
+                            bool need = false;
+                            if (idx < nm && live[0]) {
+                                const float bx0 = g.ox + (float)rx0 * h - eps, bx1 = g.ox + (float)(rx1 + 1) * h + eps;
+                                const float by0 = g.oy + (float)ry * h - eps, by1 = g.oy + (float)(ry + 1) * h + eps;
+                                const float bz0 = g.oz + (float)rz * h - eps, bz1 = g.oz + (float)(rz + 1) * h + eps;
+                                need = box_lb2(sx[0], sy[0], sz[0], bx0, bx1, by0, by1, bz0, bz1) < best[0];
+                            }
+                            const uint64_t bm = __ballot(need);
+                            const uint64_t gbits = (bm >> (lane & ~(grp - 1))) & ((1ull << grp) - 1ull);
+                            if (idx < nm && (lane & (grp - 1)) == 0 && gbits) sw_end[src] = 1u;
+                        }
+                        __builtin_amdgcn_wave_barrier();
+                        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                        need_m |= __ballot(sw_end[lane] != 0u);
+                        __builtin_amdgcn_wave_barrier();
+                        mask = 0;
+                    }
                     while (mask) {
                         const int src = __ffsll((unsigned long long)mask) - 1;
                         mask &= mask - 1;
