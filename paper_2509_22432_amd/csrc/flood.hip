@@ -422,12 +422,11 @@ __global__ __launch_bounds__(kWaveBlock) __attribute__((amdgpu_waves_per_eu(T ==
                             const uint32_t k = b0 + (uint32_t)(u * 64 + lane);
                             c[u] = make_float4(INFINITY, INFINITY, INFINITY, 0.f);
                             if (k < total) {
-                                int rr = 0, hi_r = 63;  // first run whose inclusive end exceeds k
-                                while (rr < hi_r) {
-                                    const int mid = (rr + hi_r) >> 1;
-                                    if (sw_end[mid] > k) hi_r = mid;
-                                    else rr = mid + 1;
-                                }
+                                // first run whose inclusive end exceeds k (ends are
+                                // non-decreasing; k < total, the last end): six fixed steps
+                                int rr = 0;
+#pragma unroll
+                                for (int st = 32; st > 0; st >>= 1) rr += sw_end[rr + st - 1] <= k ? st : 0;
                                 c[u] = xs[sw_p0[rr] + (k - (rr ? sw_end[rr - 1] : 0u))];
                             }
                         }
@@ -673,12 +672,9 @@ __device__ bool ring_search(const GridParam &g, const uint32_t *__restrict__ cs,
         if (lane == 0) nev += total;
         ++steps;
         for (uint32_t k0 = (uint32_t)lane * kU; k0 < total; k0 += 64 * kU) {
-            int rr = 0, hi_r = 63;  // first row whose inclusive end exceeds k0
-            while (rr < hi_r) {
-                const int mid = (rr + hi_r) >> 1;
-                if (s_end[mid] > k0) hi_r = mid;
-                else rr = mid + 1;
-            }
+            int rr = 0;  // first row whose inclusive end exceeds k0 (six fixed steps)
+#pragma unroll
+            for (int st = 32; st > 0; st >>= 1) rr += s_end[rr + st - 1] <= k0 ? st : 0;
             uint32_t pp[kU];
 #pragma unroll
             for (int u = 0; u < kU; ++u) {
