@@ -108,8 +108,10 @@ __global__ __launch_bounds__(1024) void k_bucket_base(const int64_t *s_off, int3
 __global__ void k_sample_keys(int d, SampleRule rule, int n_int, int32_t B, int64_t S, const float *__restrict__ L,
                               const int32_t *__restrict__ simp, const int64_t *__restrict__ s_off,
                               const GridParam *__restrict__ gp, const int32_t *__restrict__ mbits,
-                              const uint32_t *__restrict__ bbase, uint32_t *__restrict__ skey,
-                              uint32_t *__restrict__ counts) {
+                              const uint32_t *__restrict__ bbase, const float *__restrict__ X,
+                              const int32_t *__restrict__ l_xidx, const int64_t *__restrict__ x_off,
+                              int32_t landmarks_in_x, uint32_t *__restrict__ skey, uint32_t *__restrict__ counts,
+                              float4 *__restrict__ spos) {
     const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (gid >= S) return;
     const int64_t j = gid / n_int;
@@ -127,6 +129,18 @@ __global__ void k_sample_keys(int d, SampleRule rule, int n_int, int32_t B, int6
     simplex_vertices(simp, d, j, v);
     float sx, sy, sz;
     weighted_point(L, v, w, d, sx, sy, sz);
+    float u = INFINITY;
+    if (landmarks_in_x) {
+        // the squared distance to the vertices' own points of X (read from
+        // X, so it holds whatever the landmark array holds; a row outside
+        // the cloud gives no bound): an upper bound of the sample's value
+        const int64_t x_lo = x_off[lo_b], x_hi = x_off[lo_b + 1];
+        for (int i = 0; i <= d; ++i) {
+            const int64_t xi = l_xidx[v[i]];
+            if (xi >= x_lo && xi < x_hi) u = fminf(u, dist2(sx, sy, sz, X[3 * xi], X[3 * xi + 1], X[3 * xi + 2]));
+        }
+    }
+    spos[gid] = make_float4(sx, sy, sz, u);
     const int m = mbits[lo_b];
     const float ext = (float)max(max(g.nx, g.ny), g.nz) * g.h;
     const float sc = (float)(1 << m) / ext;
@@ -182,8 +196,7 @@ __device__ __forceinline__ void publish(uint64_t *key, const float *seed, int32_
 
 template <int T>
 __global__ __launch_bounds__(kWaveBlock) __attribute__((amdgpu_waves_per_eu(T == 1 ? 8 : 1, 8))) void k_flood_tiles(
-    TileArgs a, const float *__restrict__ L, const float *__restrict__ X, const int32_t *__restrict__ l_xidx,
-    const int64_t *__restrict__ x_off, const int32_t *__restrict__ simp, const int64_t *__restrict__ s_off,
+    TileArgs a, const float4 *__restrict__ spos, const int64_t *__restrict__ s_off,
     const int64_t *__restrict__ tile_off, const float *__restrict__ seed, uint64_t *__restrict__ key,
     const GridParam *__restrict__ gp, const uint32_t *__restrict__ cs, const float4 *__restrict__ xs,
     const uint32_t *__restrict__ order, OpenSample *__restrict__ hard, uint32_t *__restrict__ hard_count,
@@ -209,7 +222,6 @@ __global__ __launch_bounds__(kWaveBlock) __attribute__((amdgpu_waves_per_eu(T ==
     const GridParam g = gp[b];
     const int64_t sbase = s_off[b];
     const int64_t S = (s_off[b + 1] - sbase) * (int64_t)a.n_int;
-    const int64_t x_lo = x_off[b], x_hi = x_off[b + 1];
     // a tile of a.lanes samples (T = 1; 64 T otherwise); with fewer than 64,
     // lane l holds sample l mod a.lanes, a copy that scans its share of every
     // staged pass from the start (see grp below)
@@ -230,28 +242,18 @@ __global__ __launch_bounds__(kWaveBlock) __attribute__((amdgpu_waves_per_eu(T ==
         sj[t] = 0;
         sq[t] = 0;
         if (valid) {
+            // the sample's point and its bound, from the sample sort (in
+            // global sample order: simplex j's samples from j * n_int on)
             const uint32_t gid = order[sbase * a.n_int + ls];
             const int64_t j = gid / (uint32_t)a.n_int;
             const int q = (int)(gid % (uint32_t)a.n_int);
             sj[t] = (int32_t)j;
             sq[t] = q;
-            float w[4];
-            own_weights(SampleRule{a.k, a.sampling, a.seed}, d, q, j - sbase, w);
-            int32_t v[4];
-            simplex_vertices(simp, d, j, v);
-            weighted_point(L, v, w, d, sx[t], sy[t], sz[t]);
-            float u = INFINITY;
-            if (a.landmarks_in_x) {
-                // the bound is the distance to the landmark's own point of X
-                // (read from X, so it holds whatever the landmark array holds;
-                // a row outside the cloud gives no bound)
-                for (int i = 0; i <= d; ++i) {
-                    const int64_t xi = l_xidx[v[i]];
-                    if (xi >= x_lo && xi < x_hi)
-                        u = fminf(u, dist2(sx[t], sy[t], sz[t], X[3 * xi], X[3 * xi + 1], X[3 * xi + 2]));
-                }
-            }
-            best[t] = u;
+            const float4 sp = spos[gid];
+            sx[t] = sp.x;
+            sy[t] = sp.y;
+            sz[t] = sp.z;
+            best[t] = sp.w;
             M[t] = seed[j];
         }
         live[t] = valid && !(sqrt_rn(best[t]) < M[t]);
@@ -965,6 +967,7 @@ size_t flood_workspace(const flood_problem *pb, float alpha, FloodSizes *sz) {
         bkmax = bk > bkmax ? bk : bkmax;
     }
     bytes += 2 * (sizeof(uint32_t) * (smax + 1) + 256);  // sample keys and order
+    bytes += sizeof(float4) * (smax + 1) + 256;           // sample points and bounds
     bytes += 2 * (sizeof(uint32_t) * (bkmax + 1) + 256); // bucket counts and cursors
     bytes += sizeof(uint32_t) * scan_tmp_elems(bkmax + 1) + 256;
     bytes += sizeof(int32_t) * (pb->B + 1) + sizeof(uint32_t) * (pb->B + 1) + 512;
@@ -980,13 +983,12 @@ size_t flood_workspace(const flood_problem *pb, float alpha, FloodSizes *sz) {
 }
 
 template <int T>
-static void launch_tiles(const TileArgs &ta, int wpb, hipStream_t s, const flood_problem *pb, const int32_t *simp,
+static void launch_tiles(const TileArgs &ta, int wpb, hipStream_t s, const float4 *spos,
                          const int64_t *s_off, const int64_t *tile_off, const float *seed, uint64_t *key,
                          const GridWork &g, const uint32_t *order, OpenSample *hard, uint32_t *hard_count,
                          uint64_t *evals, uint64_t *stats) {
     const int64_t nb = (ta.n_tiles + wpb - 1) / wpb;
-    hipLaunchKernelGGL(k_flood_tiles<T>, dim3((unsigned)nb), dim3(64 * wpb), 0, s, ta, pb->Lxyz, pb->X, pb->l_xidx,
-                       pb->x_off_d, simp, s_off, tile_off,
+    hipLaunchKernelGGL(k_flood_tiles<T>, dim3((unsigned)nb), dim3(64 * wpb), 0, s, ta, spos, s_off, tile_off,
                        seed, key, g.gp, g.cell_start, g.xs, order, hard, hard_count, (unsigned long long *)evals,
                        (unsigned long long *)stats);
 }
@@ -1019,6 +1021,7 @@ hipError_t flood_run(const flood_problem *pb, const flood_tuning &tu, const floo
     }
     uint32_t *skey = c.take<uint32_t>(smax + 1);
     uint32_t *order = c.take<uint32_t>(smax + 1);
+    float4 *spos = c.take<float4>(smax + 1);  // sample points and bounds, in global sample order
     uint32_t *bcount = c.take<uint32_t>(bkmax + 1);
     uint32_t *bcursor = c.take<uint32_t>(bkmax + 1);
     uint32_t *bscan = c.take<uint32_t>(scan_tmp_elems(bkmax + 1));
@@ -1068,7 +1071,8 @@ hipError_t flood_run(const flood_problem *pb, const flood_tuning &tu, const floo
             e = fill_u32(bcount, 0u, bk + 1, s);
             if (e != hipSuccess) return e;
             hipLaunchKernelGGL(k_sample_keys, dim3((unsigned)((S + 255) / 256)), dim3(256), 0, s, d, rule, (int)nint,
-                               pb->B, S, pb->Lxyz, simp, soff_d, g.gp, mbits, bbase, skey, bcount);
+                               pb->B, S, pb->Lxyz, simp, soff_d, g.gp, mbits, bbase, pb->X, pb->l_xidx,
+                               pb->x_off_d, pb->landmarks_in_x, skey, bcount, spos);
             e = exclusive_scan_u32(bcount, bk + 1, bscan, s);
             if (e != hipSuccess) return e;
             e = copy_u32(bcount, bcursor, bk, s);
@@ -1093,9 +1097,9 @@ hipError_t flood_run(const flood_problem *pb, const flood_tuning &tu, const floo
                     e = hipEventRecord((hipEvent_t)out->tile_events[3 * d], s);
                     if (e != hipSuccess) return e;
                 }
-                if (T == 1) launch_tiles<1>(ta, wpb, s, pb, simp, soff_d, tile_off[d], seed, key, g, order, hard, counters, out->evals, out->stats);
-                else if (T == 2) launch_tiles<2>(ta, wpb, s, pb, simp, soff_d, tile_off[d], seed, key, g, order, hard, counters, out->evals, out->stats);
-                else launch_tiles<4>(ta, wpb, s, pb, simp, soff_d, tile_off[d], seed, key, g, order, hard, counters, out->evals, out->stats);
+                if (T == 1) launch_tiles<1>(ta, wpb, s, spos, soff_d, tile_off[d], seed, key, g, order, hard, counters, out->evals, out->stats);
+                else if (T == 2) launch_tiles<2>(ta, wpb, s, spos, soff_d, tile_off[d], seed, key, g, order, hard, counters, out->evals, out->stats);
+                else launch_tiles<4>(ta, wpb, s, spos, soff_d, tile_off[d], seed, key, g, order, hard, counters, out->evals, out->stats);
                 if (out->tile_events[3 * d + 1]) {
                     e = hipEventRecord((hipEvent_t)out->tile_events[3 * d + 1], s);
                     if (e != hipSuccess) return e;

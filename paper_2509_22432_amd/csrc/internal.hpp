@@ -50,24 +50,21 @@ __host__ __device__ inline int64_t cells_cap(int64_t n, float alpha) {
 // and receives the sum of the values of threads 0..t-1; every thread gets
 // the block total.  Called by every thread of a block of at most 1024.
 __device__ inline int64_t block_exclusive_i64(int64_t v, int64_t &total) {
+    // Hillis-Steele inclusive scan in LDS, log2(blockDim) rounds
     __shared__ int64_t s_part[1024];
-    __shared__ int64_t s_total;
-    s_part[threadIdx.x] = v;
+    const unsigned t = threadIdx.x;
+    s_part[t] = v;
     __syncthreads();
-    if (threadIdx.x == 0) {
-        int64_t acc = 0;
-        for (unsigned t = 0; t < blockDim.x; ++t) {
-            const int64_t x = s_part[t];
-            s_part[t] = acc;
-            acc += x;
-        }
-        s_total = acc;
+    for (unsigned off = 1; off < blockDim.x; off <<= 1) {
+        const int64_t x = t >= off ? s_part[t - off] : 0;
+        __syncthreads();
+        s_part[t] += x;
+        __syncthreads();
     }
+    const int64_t incl = s_part[t];
+    total = s_part[blockDim.x - 1];
     __syncthreads();
-    const int64_t r = s_part[threadIdx.x];
-    total = s_total;
-    __syncthreads();
-    return r;
+    return incl - v;
 }
 
 // Ordered-key encoding of floats for atomic min/max on unsigned ints.
