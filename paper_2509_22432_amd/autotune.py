@@ -27,6 +27,7 @@ DEFAULT_CANDIDATES = [
     {"cells_per_point": 1.0, "samples_per_lane": 1, "waves_per_block": 4, "tile_shells": 8},
     {"cells_per_point": 1.0, "samples_per_lane": 1, "waves_per_block": 4, "tile_shells": -1},
     {"cells_per_point": 1.0, "samples_per_lane": 1, "waves_per_block": 4, "tile_shells": 6, "tile_lanes": 32},
+    {"cells_per_point": 1.0, "samples_per_lane": 1, "waves_per_block": 4, "tile_shells": 8, "tile_lanes": 32},
     {"cells_per_point": 1.0, "samples_per_lane": 1, "waves_per_block": 4, "tile_shells": 6, "tile_lanes": 16},
     {"cells_per_point": 0.5, "samples_per_lane": 1, "waves_per_block": 4, "tile_shells": 6, "tile_lanes": 16},
 ]

@@ -298,21 +298,32 @@ __global__ __launch_bounds__(kWaveBlock) __attribute__((amdgpu_waves_per_eu(T ==
                          hi[2] - lo[2] < a.max_extent && a.radius_budget >= 0;
     if (compact) {
         int olo[3] = {lo[0], lo[1], lo[2]}, ohi[3] = {lo[0] - 1, lo[1] - 1, lo[2] - 1};  // empty old box
+        // live-sample bounding box (a coarse cull for the rows), recomputed
+        // only when the set of live lanes changed: a stale box is larger,
+        // which culls less but never wrongly
+        float lx0 = 0.f, lx1 = 0.f, ly0 = 0.f, ly1 = 0.f, lz0 = 0.f, lz1 = 0.f;
+        uint64_t box_live = 0;
         for (int r = 0;; ++r) {
-            // live-sample bounding box and largest bound: a coarse cull for the rows
-            float lx0 = INFINITY, lx1 = -INFINITY, ly0 = INFINITY, ly1 = -INFINITY, lz0 = INFINITY, lz1 = -INFINITY;
             float bmax = 0.f;
 #pragma unroll
             for (int t = 0; t < T; ++t)
-                if (live[t]) {
-                    lx0 = fminf(lx0, sx[t]); lx1 = fmaxf(lx1, sx[t]);
-                    ly0 = fminf(ly0, sy[t]); ly1 = fmaxf(ly1, sy[t]);
-                    lz0 = fminf(lz0, sz[t]); lz1 = fmaxf(lz1, sz[t]);
-                    bmax = fmaxf(bmax, best[t]);
-                }
-            lx0 = wave_min_f32_dpp(lx0); lx1 = wave_max_f32_dpp(lx1);
-            ly0 = wave_min_f32_dpp(ly0); ly1 = wave_max_f32_dpp(ly1);
-            lz0 = wave_min_f32_dpp(lz0); lz1 = wave_max_f32_dpp(lz1);
+                if (live[t]) bmax = fmaxf(bmax, best[t]);
+            const uint64_t now_live = __ballot(live[0]);
+            if (T > 1 || r == 0 || now_live != box_live) {
+                box_live = now_live;
+                lx0 = INFINITY; lx1 = -INFINITY; ly0 = INFINITY; ly1 = -INFINITY; lz0 = INFINITY; lz1 = -INFINITY;
+#pragma unroll
+                for (int t = 0; t < T; ++t)
+                    if (live[t]) {
+                        lx0 = fminf(lx0, sx[t]); lx1 = fmaxf(lx1, sx[t]);
+                        ly0 = fminf(ly0, sy[t]); ly1 = fmaxf(ly1, sy[t]);
+                        lz0 = fminf(lz0, sz[t]); lz1 = fmaxf(lz1, sz[t]);
+                    }
+                lx0 = wave_min_f32_dpp(lx0); lx1 = wave_max_f32_dpp(lx1);
+                ly0 = wave_min_f32_dpp(ly0); ly1 = wave_max_f32_dpp(ly1);
+                lz0 = wave_min_f32_dpp(lz0); lz1 = wave_max_f32_dpp(lz1);
+            }
+            // the largest bound falls every shell
             bmax = wave_max_f32_dpp(bmax);
             // rows of box [lo,hi] minus box [olo,ohi], enumerated 64 at a time
             const int nyb = hi[1] - lo[1] + 1;
@@ -595,21 +606,24 @@ struct DeepArgs {
 
 __device__ __forceinline__ void ring_pos(int i, int &r, int &dy, int &dz) {
     // i-th row in ring order: ring r holds 8r rows (1 for r = 0) and starts
-    // at index (2r-1)^2
-    if (i == 0) {
-        r = 0; dy = 0; dz = 0;
-        return;
-    }
+    // at index (2r-1)^2; its four sides of 2r rows each, without branches
+    // (sqrt of i + 1/2 lands within one ring of the answer; one step fixes it)
     int rr = (int)((sqrtf((float)i + 0.5f) + 1.0f) * 0.5f);
-    while ((2 * rr - 1) * (2 * rr - 1) > i) --rr;
-    while ((2 * rr + 1) * (2 * rr + 1) <= i) ++rr;
+    rr -= (2 * rr - 1) * (2 * rr - 1) > i ? 1 : 0;
+    rr += (2 * rr + 1) * (2 * rr + 1) <= i ? 1 : 0;
+    const int e = 2 * rr;
+    const int p = i - (e - 1) * (e - 1);
+    const int side = (p >= e ? 1 : 0) + (p >= 2 * e ? 1 : 0) + (p >= 3 * e ? 1 : 0);
+    const int off = p - side * e;
+    const int lo = off - rr, hi = rr - off;
+    dy = side == 0 ? lo : (side == 1 ? rr : (side == 2 ? hi : -rr));
+    dz = side == 0 ? -rr : (side == 1 ? lo : (side == 2 ? rr : hi));
+    if (i == 0) {
+        rr = 0;
+        dy = 0;
+        dz = 0;
+    }
     r = rr;
-    const int p = i - (2 * rr - 1) * (2 * rr - 1);
-    const int side = p / (2 * rr), off = p % (2 * rr);
-    if (side == 0) { dy = -rr + off; dz = -rr; }
-    else if (side == 1) { dy = rr; dz = -rr + off; }
-    else if (side == 2) { dy = rr - off; dz = rr; }
-    else { dy = -rr; dz = rr - off; }
 }
 
 __device__ __forceinline__ void lex_min(float &bd, int32_t &bi, float od, int32_t oi) {
