@@ -110,8 +110,8 @@ __global__ void k_sample_keys(int d, SampleRule rule, int n_int, int32_t B, int6
                               const GridParam *__restrict__ gp, const int32_t *__restrict__ mbits,
                               const uint32_t *__restrict__ bbase, const float *__restrict__ X,
                               const int32_t *__restrict__ l_xidx, const int64_t *__restrict__ x_off,
-                              int32_t landmarks_in_x, uint32_t *__restrict__ skey, uint32_t *__restrict__ counts,
-                              float4 *__restrict__ spos) {
+                              int32_t landmarks_in_x, uint32_t *__restrict__ skey, uint32_t *__restrict__ srank,
+                              uint32_t *__restrict__ counts, float4 *__restrict__ spos) {
     const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (gid >= S) return;
     const int64_t j = gid / n_int;
@@ -150,14 +150,14 @@ __global__ void k_sample_keys(int d, SampleRule rule, int n_int, int32_t B, int6
     const int qz = min(max((int)((sz - g.oz) * sc), 0), top);
     const uint32_t key = bbase[lo_b] + (spread3(qx) | (spread3(qy) << 1) | (spread3(qz) << 2));
     skey[gid] = key;
-    atomicAdd(&counts[key], 1u);
+    srank[gid] = atomicAdd(&counts[key], 1u);  // the sample's place in its bucket
 }
 
-__global__ void k_sample_scatter(int64_t S, const uint32_t *__restrict__ skey, uint32_t *__restrict__ cursor,
-                                 uint32_t *__restrict__ order) {
+__global__ void k_sample_scatter(int64_t S, const uint32_t *__restrict__ skey, const uint32_t *__restrict__ srank,
+                                 const uint32_t *__restrict__ bstart, uint32_t *__restrict__ order) {
     const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (gid >= S) return;
-    order[atomicAdd(&cursor[skey[gid]], 1u)] = (uint32_t)gid;
+    order[bstart[skey[gid]] + srank[gid]] = (uint32_t)gid;
 }
 
 // ---------------------------------------------------------------------------
@@ -848,38 +848,71 @@ __global__ __launch_bounds__(256) void k_match_winners(const OpenSample *__restr
     }
 }
 
-// x* of the winning own sample of every simplex (one wave per simplex): the
-// value is known, so the search ball is exact and tiny for most simplices
+// simplices still needing x* (an own sample won and no per-sample search
+// gave its point): a list in kQueues regions, region c filled by the
+// workgroups b = c mod kQueues (so its size is bounded by the simplices those
+// workgroups cover, cap each), one atomic per wavefront on the region's count
+__host__ __device__ __forceinline__ int64_t winner_region_cap(int64_t n) {
+    return ((n + 255) / 256 + kQueues - 1) / kQueues * 256;
+}
+__global__ __launch_bounds__(256) void k_winner_list(int64_t n, const uint64_t *__restrict__ key,
+                                                     uint32_t *__restrict__ wcount, uint32_t *__restrict__ wlist) {
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int lane = threadIdx.x & 63;
+    const bool need = j < n && key[j] != 0;
+    const uint64_t m = __ballot(need);
+    if (!m) return;
+    const uint32_t c = blockIdx.x % kQueues;
+    uint32_t base = 0;
+    if (lane == 0) base = atomicAdd(&wcount[c * kCursorStride], (uint32_t)__popcll(m));
+    base = __shfl(base, 0, 64);
+    if (need) wlist[c * winner_region_cap(n) + base + __popcll(m & ((1ull << lane) - 1ull))] = (uint32_t)j;
+}
+
+// x* of the winning own sample of the listed simplices: persistent
+// wavefronts take list entries through the region cursors; the value is
+// known, so the search ball is exact and tiny for most simplices
 __global__ __launch_bounds__(kWaveBlock) void k_winner_search(
     int d, SampleRule rule, int64_t n, int32_t B, const float *__restrict__ L, const int32_t *__restrict__ simp,
     const int64_t *__restrict__ s_off, const uint64_t *__restrict__ key, const GridParam *__restrict__ gp,
     const uint32_t *__restrict__ cs, const uint32_t *__restrict__ occ, const float4 *__restrict__ xs,
+    const uint32_t *__restrict__ wcount, uint32_t *__restrict__ wnext, const uint32_t *__restrict__ wlist,
     int32_t *__restrict__ win_x) {
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     __shared__ uint32_t s_p0[kWaveBlock / 64][64], s_end[kWaveBlock / 64][64];
-    const int64_t j = xcd_remap(blockIdx.x, gridDim.x) * (blockDim.x >> 6) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    if (j >= n) return;
-    const uint64_t kv = key[j];
-    if (kv == 0) return;
-    const int q = (int)(0xffffffffu - (uint32_t)(kv & 0xffffffffu));
-    const int b = find_cloud(s_off, B, j);
-    float w[4];
-    own_weights(rule, d, q, j - s_off[b], w);
-    int32_t v[4];
-    simplex_vertices(simp, d, j, v);
-    float sx, sy, sz;
-    weighted_point(L, v, w, d, sx, sy, sz);
-    const float val = key_value(kv);
-    const float rb = val * (1.0f + 1e-6f) + 1e-30f;
-    float bd = rb * rb;
-    int32_t bi = 0x7fffffff;
-    float M = 0.f;
-    unsigned long long nev = 0;
-    uint32_t nsteps = 0;
-    const GridParam g = gp[b];
-    ring_search<true>(g, cs, occ, xs, sx, sy, sz, bd, bi, false, M, nullptr, s_p0[wid], s_end[wid], lane, nev,
-                      nsteps);
-    if (lane == 0) win_x[j] = bi;
+    const uint32_t c = blockIdx.x % kQueues;
+    const uint32_t cnt = wcount[c * kCursorStride];
+    const uint32_t grab = cnt > (1u << 15) ? kGrab : 1u;
+    const uint32_t *list = wlist + c * winner_region_cap(n);
+    while (true) {
+        uint32_t v0 = 0;
+        if (lane == 0) v0 = atomicAdd(&wnext[c * kCursorStride], grab);
+        v0 = __builtin_amdgcn_readfirstlane(v0);
+        if (v0 >= cnt) break;
+        for (uint32_t u = 0; u < grab && v0 + u < cnt; ++u) {
+            const int64_t j = __builtin_amdgcn_readfirstlane(list[v0 + u]);
+            const uint64_t kv = key[j];
+            const int q = (int)(0xffffffffu - (uint32_t)(kv & 0xffffffffu));
+            const int b = find_cloud(s_off, B, j);
+            float w[4];
+            own_weights(rule, d, q, j - s_off[b], w);
+            int32_t v[4];
+            simplex_vertices(simp, d, j, v);
+            float sx, sy, sz;
+            weighted_point(L, v, w, d, sx, sy, sz);
+            const float val = key_value(kv);
+            const float rb = val * (1.0f + 1e-6f) + 1e-30f;
+            float bd = rb * rb;
+            int32_t bi = 0x7fffffff;
+            float M = 0.f;
+            unsigned long long nev = 0;
+            uint32_t nsteps = 0;
+            const GridParam g = gp[b];
+            ring_search<true>(g, cs, occ, xs, sx, sy, sz, bd, bi, false, M, nullptr, s_p0[wid], s_end[wid], lane, nev,
+                              nsteps);
+            if (lane == 0) win_x[j] = bi;
+        }
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -982,7 +1015,10 @@ size_t flood_workspace(const flood_problem *pb, float alpha, FloodSizes *sz) {
     }
     bytes += 2 * (sizeof(uint32_t) * (smax + 1) + 256);  // sample keys and order
     bytes += sizeof(float4) * (smax + 1) + 256;           // sample points and bounds
-    bytes += 2 * (sizeof(uint32_t) * (bkmax + 1) + 256); // bucket counts and cursors
+    bytes += sizeof(uint32_t) * (bkmax + 1) + 256;       // bucket counts (then starts)
+    bytes += sizeof(uint32_t) * (smax + 1) + 256;        // sample ranks within their buckets
+    bytes += sizeof(uint32_t) * 2 * kCursorStride * kQueues + 256;  // winner list counts and cursors
+    bytes += sizeof(uint32_t) * kQueues * winner_region_cap(nmax) + 256;  // winner list
     bytes += sizeof(uint32_t) * scan_tmp_elems(bkmax + 1) + 256;
     bytes += sizeof(int32_t) * (pb->B + 1) + sizeof(uint32_t) * (pb->B + 1) + 512;
     bytes += sizeof(uint32_t) * kCursorStride * (kQueues + 1) + 256;  // queue count and cursors
@@ -1037,7 +1073,10 @@ hipError_t flood_run(const flood_problem *pb, const flood_tuning &tu, const floo
     uint32_t *order = c.take<uint32_t>(smax + 1);
     float4 *spos = c.take<float4>(smax + 1);  // sample points and bounds, in global sample order
     uint32_t *bcount = c.take<uint32_t>(bkmax + 1);
-    uint32_t *bcursor = c.take<uint32_t>(bkmax + 1);
+    uint32_t *srank = c.take<uint32_t>(smax + 1);
+    // the winner search's list: region counts, then region cursors (kCursorStride apart); the list
+    uint32_t *wcounters = c.take<uint32_t>(2 * kCursorStride * kQueues);
+    uint32_t *wlist = c.take<uint32_t>(kQueues * winner_region_cap(nmax));
     uint32_t *bscan = c.take<uint32_t>(scan_tmp_elems(bkmax + 1));
     int32_t *mbits = c.take<int32_t>(pb->B + 1);
     uint32_t *bbase = c.take<uint32_t>(pb->B + 1);
@@ -1086,13 +1125,11 @@ hipError_t flood_run(const flood_problem *pb, const flood_tuning &tu, const floo
             if (e != hipSuccess) return e;
             hipLaunchKernelGGL(k_sample_keys, dim3((unsigned)((S + 255) / 256)), dim3(256), 0, s, d, rule, (int)nint,
                                pb->B, S, pb->Lxyz, simp, soff_d, g.gp, mbits, bbase, pb->X, pb->l_xidx,
-                               pb->x_off_d, pb->landmarks_in_x, skey, bcount, spos);
-            e = exclusive_scan_u32(bcount, bk + 1, bscan, s);
+                               pb->x_off_d, pb->landmarks_in_x, skey, srank, bcount, spos);
+            e = exclusive_scan_u32(bcount, bk + 1, bscan, s);  // bucket starts
             if (e != hipSuccess) return e;
-            e = copy_u32(bcount, bcursor, bk, s);
-            if (e != hipSuccess) return e;
-            hipLaunchKernelGGL(k_sample_scatter, dim3((unsigned)((S + 255) / 256)), dim3(256), 0, s, S, skey, bcursor,
-                               order);
+            hipLaunchKernelGGL(k_sample_scatter, dim3((unsigned)((S + 255) / 256)), dim3(256), 0, s, S, skey, srank,
+                               bcount, order);
             if (ntiles > 0) {
                 TileArgs ta;
                 ta.d = d;
@@ -1142,8 +1179,12 @@ hipError_t flood_run(const flood_problem *pb, const flood_tuning &tu, const floo
         if (nint > 0 && ntiles_d > 0)
             hipLaunchKernelGGL(k_match_winners, dim3(1024), dim3(256), 0, s, hard, counters, (int32_t)nint, key,
                                out->win_x[d]);
-        hipLaunchKernelGGL(k_winner_search, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, s, d, rule, n, pb->B,
-                           pb->Lxyz, simp, soff_d, key, g.gp, g.cell_start, g.occ, g.xs, out->win_x[d]);
+        e = fill_u32(wcounters, 0u, 2 * kCursorStride * kQueues, s);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(k_winner_list, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, key, wcounters, wlist);
+        hipLaunchKernelGGL(k_winner_search, dim3(2048), dim3(256), 0, s, d, rule, n, pb->B, pb->Lxyz, simp, soff_d,
+                           key, g.gp, g.cell_start, g.occ, g.xs, wcounters, wcounters + kCursorStride * kQueues,
+                           wlist, out->win_x[d]);
         e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
