@@ -150,7 +150,20 @@ __global__ void k_sample_keys(int d, SampleRule rule, int n_int, int32_t B, int6
     const int qz = min(max((int)((sz - g.oz) * sc), 0), top);
     const uint32_t key = bbase[lo_b] + (spread3(qx) | (spread3(qy) << 1) | (spread3(qz) << 2));
     skey[gid] = key;
-    srank[gid] = atomicAdd(&counts[key], 1u);  // the sample's place in its bucket
+    // the sample's place in its bucket: one atomic per distinct key of the
+    // wavefront (neighbouring samples share buckets)
+    const int lane = threadIdx.x & 63;
+    uint64_t todo = __ballot(true);
+    while (todo) {
+        const int ldr = __ffsll((unsigned long long)todo) - 1;
+        const uint32_t kl = __builtin_amdgcn_readlane(key, ldr);
+        const uint64_t same = __ballot(key == kl) & todo;
+        uint32_t base = 0;
+        if (lane == ldr) base = atomicAdd(&counts[kl], (uint32_t)__popcll(same));
+        base = __shfl(base, ldr, 64);
+        if ((same >> lane) & 1ull) srank[gid] = base + (uint32_t)__popcll(same & ((1ull << lane) - 1ull));
+        todo &= ~same;
+    }
 }
 
 __global__ void k_sample_scatter(int64_t S, const uint32_t *__restrict__ skey, const uint32_t *__restrict__ srank,

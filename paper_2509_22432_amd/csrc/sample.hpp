@@ -6,11 +6,13 @@
 
 namespace flood {
 
-// Morton resolution (bits per axis) of the sample sort: about four samples
-// per bucket on a 2^m cube
+// Morton resolution (bits per axis) of the sample sort: 2 to 16 samples per
+// bucket of a 2^m cube on average (a tile spans a few buckets; neighbouring
+// samples share a bucket, so the counting pass takes one atomic per bucket
+// and wavefront)
 __host__ __device__ inline int morton_bits(int64_t S) {
     int m = 1;
-    while (m < 8 && ((int64_t)4 << (3 * m)) < S) ++m;
+    while (m < 8 && ((int64_t)16 << (3 * m)) < S) ++m;
     return m;
 }
 
