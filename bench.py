@@ -619,7 +619,7 @@ def differentiable_block(args, reps):
 # ---------------------------------------------------------------------------
 # swiss-cheese stage breakdown and scaling sweeps
 
-def one_pipeline(torch, P, X, n_lm, k, reps=3):
+def one_pipeline(torch, P, X, n_lm, k, reps=3, tuning=None):
     """FPS + Del(L) + filtration + persistence of one cloud; median times."""
     Xd = torch.from_numpy(X).cuda()
     e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
@@ -631,7 +631,13 @@ def one_pipeline(torch, P, X, n_lm, k, reps=3):
     del_ms = (time.time() - t0) * 1e3
     pb = P.problem_from_complexes(Xd, [0, len(X)], Xd[idx.long()].contiguous(), [0, n_lm], [cx], k,
                                   l_xidx=idx.clone())
-    run = P.api.FloodRun(pb, None, count_evals=False)
+    if tuning is None:
+        # the autotuner on this problem (without the candidate that skips the
+        # tile search, which hands every sample to the per-sample search)
+        from paper_2509_22432_amd import autotune
+        tuning, _ = autotune.autotune(pb, [c for c in autotune.DEFAULT_CANDIDATES if c.get("tile_shells") != -1],
+                                      use_cache=False)
+    run = P.api.FloodRun(pb, tuning, count_evals=False)
     hev = HipEvents(2)
     run.out.grid_events[0], run.out.grid_events[1] = hev.ev[0].value, hev.ev[1].value
     fps_ms, fl_ms, gr_ms = [], [], []
@@ -652,7 +658,7 @@ def one_pipeline(torch, P, X, n_lm, k, reps=3):
     P.persistence(cx, f)
     ph_ms = (time.time() - t0) * 1e3
     med = lambda v: float(np.median(v[1:]))
-    res = {"N": len(X), "L": n_lm, "k": k, "simplices": list(cx.counts()), "fps_ms": med(fps_ms),
+    res = {"N": len(X), "L": n_lm, "k": k, "tuning": tuning, "simplices": list(cx.counts()), "fps_ms": med(fps_ms),
            "delaunay_host_ms": del_ms, "grid_build_ms": med(gr_ms), "filtration_ms": med(fl_ms) - med(gr_ms),
            "persistence_host_ms": ph_ms}
     res["total_ms"] = res["fps_ms"] + del_ms + med(fl_ms) + ph_ms
@@ -664,29 +670,30 @@ def one_pipeline(torch, P, X, n_lm, k, reps=3):
 def sweep(args, torch, P, synth):
     rows = []
     k = args.sweep_k
+    tu = json.loads(args.tuning) if args.tuning else None
     if args.sweep in ("x", "all"):
         for n in (10_000, 30_000, 100_000, 300_000, 1_000_000, 3_000_000, 10_000_000):
             X, _, _ = synth.swisscheese(n, 10, seed=2000)
-            rows.append(dict(sweep="|X| at |L|=1k", **one_pipeline(torch, P, X, 1000, k)))
+            rows.append(dict(sweep="|X| at |L|=1k", **one_pipeline(torch, P, X, 1000, k, tuning=tu)))
             print("sweep x:", rows[-1], file=sys.stderr, flush=True)
     if args.sweep in ("l", "all"):
         X, _, _ = synth.swisscheese(1_000_000, 10, seed=2000)
         for nl in (250, 500, 1000, 2000, 4000, 8000, 16000):
-            rows.append(dict(sweep="|L| at |X|=1M", **one_pipeline(torch, P, X, nl, k)))
+            rows.append(dict(sweep="|L| at |X|=1M", **one_pipeline(torch, P, X, nl, k, tuning=tu)))
             print("sweep l:", rows[-1], file=sys.stderr, flush=True)
     if args.sweep in ("table", "all"):
         X, _, _ = synth.swisscheese(1_000_000, 10, seed=2000)
-        rows.append(dict(sweep="Table 1: swisscheese 1M / 2k", **one_pipeline(torch, P, X, 2000, k)))
+        rows.append(dict(sweep="Table 1: swisscheese 1M / 2k", **one_pipeline(torch, P, X, 2000, k, tuning=tu)))
         print("table:", rows[-1], file=sys.stderr, flush=True)
         X = synth.config_cloud(3)
         for nl in (2000, 10_000):
-            rows.append(dict(sweep="Table 1: mix20 10M / %dk" % (nl // 1000), **one_pipeline(torch, P, X, nl, k)))
+            rows.append(dict(sweep="Table 1: mix20 10M / %dk" % (nl // 1000), **one_pipeline(torch, P, X, nl, k, tuning=tu)))
             print("table:", rows[-1], file=sys.stderr, flush=True)
     for r in rows:
         tot = r["total_ms"]
         r["share_pct"] = {s: 100 * r[s + "_ms"] / tot for s in ("fps", "delaunay_host", "grid_build", "filtration",
                                                                 "persistence_host")}
-    res = {"k": k, "points_per_edge": k + 1, "workload": "swiss-cheese clouds: uniform in [0,5]^3 minus 10 disjoint "
+    res = {"k": k, "points_per_edge": k + 1, "tuning": tu or "autotuned per row", "workload": "swiss-cheese clouds: uniform in [0,5]^3 minus 10 disjoint "
                                                            "balls of radius U[0.1, 0.5] (seed 2000)", "rows": rows}
     with open(args.sweep_out, "w") as fh:
         json.dump(res, fh, indent=1)

@@ -78,7 +78,7 @@ const char *flood_last_error(void);
  * EDEGENERATE cannot be detected before the run: if a cloud has fewer
  * distinct points than landmarks, its remaining indices repeat an earlier
  * landmark and its radius reaches 0; callers check radius.
- * Clouds of at least 2^19 points (2^14 in calls of at most 8 clouds) run
+ * Clouds of at least 2^19 points (2^12 in calls of at most 8 clouds) run
  * as one cooperative launch each (one workgroup per CU exchanging candidates
  * through the workspace); the other clouds share one launch with a
  * workgroup per cloud.  The call

@@ -464,7 +464,7 @@ __global__ __launch_bounds__(kPT) void k_fps_persist(
 static constexpr int kMaxCpw = 2560;              // chunk slots per workgroup (60 B of LDS each)
 static constexpr int kG = 8;                      // consecutive chunk slots of a workgroup under one group bound
 static constexpr int64_t kCoopMin = 1 << 19;      // clouds of at least this many points
-static constexpr int64_t kCoopMinFew = 1 << 14;   // ... or of this many, in calls of at most kFewClouds clouds
+static constexpr int64_t kCoopMinFew = 1 << 12;   // ... or of this many, in calls of at most kFewClouds clouds
 static constexpr int32_t kFewClouds = 8;
 static constexpr int kSpinLimit = 1 << 22;        // polls of one exchange before the launch gives up
 static constexpr int kK = 2;                      // candidates a workgroup publishes

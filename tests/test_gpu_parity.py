@@ -54,7 +54,7 @@ def test_fps_lattice_ties_and_start():
 
 @pytest.mark.parametrize("n_clouds", [7, 12])
 def test_fps_batched_bitexact(n_clouds):
-    # 7 clouds: those of at least 2^14 points take cooperative launches, the
+    # 7 clouds: those of at least 2^12 points take cooperative launches, the
     # others one workgroup each, in the same call; 12 clouds: all of them
     # one workgroup each
     clouds, lms = synth.batched_clouds(n_clouds, seed=4242, scale=0.2)
