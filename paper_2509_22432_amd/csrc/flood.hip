@@ -49,6 +49,22 @@ static constexpr uint32_t kNoRow = 0xffffffffu;
 
 // tile offsets per cloud: tiles_b = ceil(n_b * n_int / (64 T)) (one block,
 // a thread per cloud in rounds)
+// the cloud of every tile (batched calls): a binary search over the tile
+// offsets once per tile here, instead of a chain of dependent loads at the
+// start of every tile wavefront
+__global__ void k_tile_cloud(const int64_t *__restrict__ tile_off, int32_t B, int64_t n_tiles,
+                             uint32_t *__restrict__ tcloud) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n_tiles) return;
+    int lo_b = 0, hi_b = B;
+    while (hi_b - lo_b > 1) {
+        const int mid = (lo_b + hi_b) >> 1;
+        if (tile_off[mid] <= t) lo_b = mid;
+        else hi_b = mid;
+    }
+    tcloud[t] = (uint32_t)lo_b;
+}
+
 __global__ __launch_bounds__(1024) void k_tile_off(const int64_t *s_off, int32_t B, int64_t n_int,
                                                     int64_t tile_samples, int64_t *tile_off) {
     int64_t carry = 0;
@@ -210,7 +226,8 @@ __device__ __forceinline__ void publish(uint64_t *key, const float *seed, int32_
 template <int T>
 __global__ __launch_bounds__(kWaveBlock) __attribute__((amdgpu_waves_per_eu(T == 1 ? 8 : 1, 8))) void k_flood_tiles(
     TileArgs a, const float4 *__restrict__ spos, const int64_t *__restrict__ s_off,
-    const int64_t *__restrict__ tile_off, const float *__restrict__ seed, uint64_t *__restrict__ key,
+    const int64_t *__restrict__ tile_off, const uint32_t *__restrict__ tcloud, const float *__restrict__ seed,
+    uint64_t *__restrict__ key,
     const GridParam *__restrict__ gp, const uint32_t *__restrict__ cs, const float4 *__restrict__ xs,
     const uint32_t *__restrict__ order, OpenSample *__restrict__ hard, uint32_t *__restrict__ hard_count,
     unsigned long long *__restrict__ evals, unsigned long long *__restrict__ stats) {
@@ -225,13 +242,7 @@ __global__ __launch_bounds__(kWaveBlock) __attribute__((amdgpu_waves_per_eu(T ==
     // tile state in scalar registers
     const int64_t wave = xcd_remap(blockIdx.x, gridDim.x) * wpb + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     if (wave >= a.n_tiles) return;
-    int lo_b = 0, hi_b = a.B;
-    while (hi_b - lo_b > 1) {
-        int mid = (lo_b + hi_b) >> 1;
-        if (tile_off[mid] <= wave) lo_b = mid;
-        else hi_b = mid;
-    }
-    const int b = lo_b;
+    const int b = a.B == 1 ? 0 : (int)__builtin_amdgcn_readfirstlane(tcloud[wave]);
     const GridParam g = gp[b];
     const int64_t sbase = s_off[b];
     const int64_t S = (s_off[b + 1] - sbase) * (int64_t)a.n_int;
@@ -868,8 +879,9 @@ __global__ __launch_bounds__(256) void k_match_winners(const OpenSample *__restr
 __host__ __device__ __forceinline__ int64_t winner_region_cap(int64_t n) {
     return ((n + 255) / 256 + kQueues - 1) / kQueues * 256;
 }
-__global__ __launch_bounds__(256) void k_winner_list(int64_t n, const uint64_t *__restrict__ key,
-                                                     uint32_t *__restrict__ wcount, uint32_t *__restrict__ wlist) {
+__global__ __launch_bounds__(256) void k_winner_list(int64_t n, int32_t B, const int64_t *__restrict__ s_off,
+                                                     const uint64_t *__restrict__ key, uint32_t *__restrict__ wcount,
+                                                     uint32_t *__restrict__ wlist, uint32_t *__restrict__ wcloud) {
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int lane = threadIdx.x & 63;
     const bool need = j < n && key[j] != 0;
@@ -879,24 +891,27 @@ __global__ __launch_bounds__(256) void k_winner_list(int64_t n, const uint64_t *
     uint32_t base = 0;
     if (lane == 0) base = atomicAdd(&wcount[c * kCursorStride], (uint32_t)__popcll(m));
     base = __shfl(base, 0, 64);
-    if (need) wlist[c * winner_region_cap(n) + base + __popcll(m & ((1ull << lane) - 1ull))] = (uint32_t)j;
+    if (need) {
+        const int64_t at = c * winner_region_cap(n) + base + __popcll(m & ((1ull << lane) - 1ull));
+        wlist[at] = (uint32_t)j;
+        wcloud[at] = (uint32_t)find_cloud(s_off, B, j);
+    }
 }
 
 // x* of the winning own sample of the listed simplices: persistent
 // wavefronts take list entries through the region cursors; the value is
 // known, so the search ball is exact and tiny for most simplices
 __global__ __launch_bounds__(kWaveBlock) void k_winner_search(
-    int d, SampleRule rule, int64_t n, int32_t B, const float *__restrict__ L, const int32_t *__restrict__ simp,
-    const int64_t *__restrict__ s_off, const uint64_t *__restrict__ key, const GridParam *__restrict__ gp,
-    const uint32_t *__restrict__ cs, const uint32_t *__restrict__ occ, const float4 *__restrict__ xs,
-    const uint32_t *__restrict__ wcount, uint32_t *__restrict__ wnext, const uint32_t *__restrict__ wlist,
-    int32_t *__restrict__ win_x) {
+    int64_t n, int32_t n_int, const float4 *__restrict__ spos, const uint64_t *__restrict__ key,
+    const GridParam *__restrict__ gp, const uint32_t *__restrict__ cs, const uint32_t *__restrict__ occ,
+    const float4 *__restrict__ xs, const uint32_t *__restrict__ wcount, uint32_t *__restrict__ wnext,
+    const uint32_t *__restrict__ wlist, const uint32_t *__restrict__ wcloud, int32_t *__restrict__ win_x) {
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     __shared__ uint32_t s_p0[kWaveBlock / 64][64], s_end[kWaveBlock / 64][64];
     const uint32_t c = blockIdx.x % kQueues;
     const uint32_t cnt = wcount[c * kCursorStride];
     const uint32_t grab = cnt > (1u << 15) ? kGrab : 1u;
-    const uint32_t *list = wlist + c * winner_region_cap(n);
+    const uint32_t *list = wlist + c * winner_region_cap(n), *lcloud = wcloud + c * winner_region_cap(n);
     while (true) {
         uint32_t v0 = 0;
         if (lane == 0) v0 = atomicAdd(&wnext[c * kCursorStride], grab);
@@ -904,15 +919,12 @@ __global__ __launch_bounds__(kWaveBlock) void k_winner_search(
         if (v0 >= cnt) break;
         for (uint32_t u = 0; u < grab && v0 + u < cnt; ++u) {
             const int64_t j = __builtin_amdgcn_readfirstlane(list[v0 + u]);
+            const int b = (int)__builtin_amdgcn_readfirstlane(lcloud[v0 + u]);
             const uint64_t kv = key[j];
             const int q = (int)(0xffffffffu - (uint32_t)(kv & 0xffffffffu));
-            const int b = find_cloud(s_off, B, j);
-            float w[4];
-            own_weights(rule, d, q, j - s_off[b], w);
-            int32_t v[4];
-            simplex_vertices(simp, d, j, v);
-            float sx, sy, sz;
-            weighted_point(L, v, w, d, sx, sy, sz);
+            // the winning sample's point, as the sample sort computed it
+            const float4 sp = spos[j * n_int + q];
+            const float sx = sp.x, sy = sp.y, sz = sp.z;
             const float val = key_value(kv);
             const float rb = val * (1.0f + 1e-6f) + 1e-30f;
             float bd = rb * rb;
@@ -1031,11 +1043,12 @@ size_t flood_workspace(const flood_problem *pb, float alpha, FloodSizes *sz) {
     bytes += sizeof(uint32_t) * (bkmax + 1) + 256;       // bucket counts (then starts)
     bytes += sizeof(uint32_t) * (smax + 1) + 256;        // sample ranks within their buckets
     bytes += sizeof(uint32_t) * 2 * kCursorStride * kQueues + 256;  // winner list counts and cursors
-    bytes += sizeof(uint32_t) * kQueues * winner_region_cap(nmax) + 256;  // winner list
+    bytes += 2 * (sizeof(uint32_t) * kQueues * winner_region_cap(nmax) + 256);  // winner list and clouds
     bytes += sizeof(uint32_t) * scan_tmp_elems(bkmax + 1) + 256;
     bytes += sizeof(int32_t) * (pb->B + 1) + sizeof(uint32_t) * (pb->B + 1) + 512;
     bytes += sizeof(uint32_t) * kCursorStride * (kQueues + 1) + 256;  // queue count and cursors
     bytes += 4 * (sizeof(int64_t) * (pb->B + 1) + 256); // tile offsets
+    bytes += sizeof(uint32_t) * (smax / 16 + pb->B + 1) + 256;  // the cloud of every tile
     bytes += 1024;
     if (sz) {
         for (int d = 0; d < 4; ++d) sz->n[d] = n[d];
@@ -1047,12 +1060,13 @@ size_t flood_workspace(const flood_problem *pb, float alpha, FloodSizes *sz) {
 
 template <int T>
 static void launch_tiles(const TileArgs &ta, int wpb, hipStream_t s, const float4 *spos,
-                         const int64_t *s_off, const int64_t *tile_off, const float *seed, uint64_t *key,
+                         const int64_t *s_off, const int64_t *tile_off, const uint32_t *tcloud, const float *seed,
+                         uint64_t *key,
                          const GridWork &g, const uint32_t *order, OpenSample *hard, uint32_t *hard_count,
                          uint64_t *evals, uint64_t *stats) {
     const int64_t nb = (ta.n_tiles + wpb - 1) / wpb;
     hipLaunchKernelGGL(k_flood_tiles<T>, dim3((unsigned)nb), dim3(64 * wpb), 0, s, ta, spos, s_off, tile_off,
-                       seed, key, g.gp, g.cell_start, g.xs, order, hard, hard_count, (unsigned long long *)evals,
+                       tcloud, seed, key, g.gp, g.cell_start, g.xs, order, hard, hard_count, (unsigned long long *)evals,
                        (unsigned long long *)stats);
 }
 
@@ -1090,11 +1104,13 @@ hipError_t flood_run(const flood_problem *pb, const flood_tuning &tu, const floo
     // the winner search's list: region counts, then region cursors (kCursorStride apart); the list
     uint32_t *wcounters = c.take<uint32_t>(2 * kCursorStride * kQueues);
     uint32_t *wlist = c.take<uint32_t>(kQueues * winner_region_cap(nmax));
+    uint32_t *wcloud = c.take<uint32_t>(kQueues * winner_region_cap(nmax));  // the listed simplices' clouds
     uint32_t *bscan = c.take<uint32_t>(scan_tmp_elems(bkmax + 1));
     int32_t *mbits = c.take<int32_t>(pb->B + 1);
     uint32_t *bbase = c.take<uint32_t>(pb->B + 1);
     int64_t *tile_off[4];
     for (int d = 0; d < 4; ++d) tile_off[d] = c.take<int64_t>(pb->B + 1);
+    uint32_t *tcloud = c.take<uint32_t>(smax / 16 + pb->B + 1);  // tiles have at least 16 samples
     if (!c.ok()) return hipErrorOutOfMemory;
 
     hipError_t e = hipSuccess;
@@ -1129,6 +1145,9 @@ hipError_t flood_run(const flood_problem *pb, const flood_tuning &tu, const floo
             for (int32_t b = 0; b < pb->B; ++b) ntiles += ((soff_h[b + 1] - soff_h[b]) * nint + tsamp - 1) / tsamp;
             ntiles_d = ntiles;
             hipLaunchKernelGGL(k_tile_off, dim3(1), dim3(1024), 0, s, soff_d, pb->B, nint, tsamp, tile_off[d]);
+            if (pb->B > 1 && ntiles > 0)
+                hipLaunchKernelGGL(k_tile_cloud, dim3((unsigned)((ntiles + 255) / 256)), dim3(256), 0, s, tile_off[d],
+                                   pb->B, ntiles, tcloud);
             // spatial order of the samples
             int64_t bk = 0;
             for (int32_t b = 0; b < pb->B; ++b) bk += (int64_t)1 << (3 * morton_bits((soff_h[b + 1] - soff_h[b]) * nint));
@@ -1161,9 +1180,9 @@ hipError_t flood_run(const flood_problem *pb, const flood_tuning &tu, const floo
                     e = hipEventRecord((hipEvent_t)out->tile_events[3 * d], s);
                     if (e != hipSuccess) return e;
                 }
-                if (T == 1) launch_tiles<1>(ta, wpb, s, spos, soff_d, tile_off[d], seed, key, g, order, hard, counters, out->evals, out->stats);
-                else if (T == 2) launch_tiles<2>(ta, wpb, s, spos, soff_d, tile_off[d], seed, key, g, order, hard, counters, out->evals, out->stats);
-                else launch_tiles<4>(ta, wpb, s, spos, soff_d, tile_off[d], seed, key, g, order, hard, counters, out->evals, out->stats);
+                if (T == 1) launch_tiles<1>(ta, wpb, s, spos, soff_d, tile_off[d], tcloud, seed, key, g, order, hard, counters, out->evals, out->stats);
+                else if (T == 2) launch_tiles<2>(ta, wpb, s, spos, soff_d, tile_off[d], tcloud, seed, key, g, order, hard, counters, out->evals, out->stats);
+                else launch_tiles<4>(ta, wpb, s, spos, soff_d, tile_off[d], tcloud, seed, key, g, order, hard, counters, out->evals, out->stats);
                 if (out->tile_events[3 * d + 1]) {
                     e = hipEventRecord((hipEvent_t)out->tile_events[3 * d + 1], s);
                     if (e != hipSuccess) return e;
@@ -1194,10 +1213,11 @@ hipError_t flood_run(const flood_problem *pb, const flood_tuning &tu, const floo
                                out->win_x[d]);
         e = fill_u32(wcounters, 0u, 2 * kCursorStride * kQueues, s);
         if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(k_winner_list, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, key, wcounters, wlist);
-        hipLaunchKernelGGL(k_winner_search, dim3(2048), dim3(256), 0, s, d, rule, n, pb->B, pb->Lxyz, simp, soff_d,
-                           key, g.gp, g.cell_start, g.occ, g.xs, wcounters, wcounters + kCursorStride * kQueues,
-                           wlist, out->win_x[d]);
+        hipLaunchKernelGGL(k_winner_list, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, pb->B, soff_d, key,
+                           wcounters, wlist, wcloud);
+        hipLaunchKernelGGL(k_winner_search, dim3(2048), dim3(256), 0, s, n, (int32_t)nint, spos, key, g.gp,
+                           g.cell_start, g.occ, g.xs, wcounters, wcounters + kCursorStride * kQueues, wlist, wcloud,
+                           out->win_x[d]);
         e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
