@@ -121,8 +121,23 @@ __global__ __launch_bounds__(1024) void k_bucket_base(const int64_t *s_off, int3
     if (threadIdx.x == 0) bbase[B] = (uint32_t)carry;
 }
 
+// the cloud of every simplex of a dimension (batched calls), once per
+// simplex instead of once per sample
+__global__ void k_simplex_cloud(const int64_t *__restrict__ s_off, int32_t B, int64_t n, uint32_t *__restrict__ scloud) {
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    int lo_b = 0, hi_b = B;
+    while (hi_b - lo_b > 1) {
+        const int mid = (lo_b + hi_b) >> 1;
+        if (s_off[mid] <= j) lo_b = mid;
+        else hi_b = mid;
+    }
+    scloud[j] = (uint32_t)lo_b;
+}
+
 __global__ void k_sample_keys(int d, SampleRule rule, int n_int, int32_t B, int64_t S, const float *__restrict__ L,
                               const int32_t *__restrict__ simp, const int64_t *__restrict__ s_off,
+                              const uint32_t *__restrict__ scloud,
                               const GridParam *__restrict__ gp, const int32_t *__restrict__ mbits,
                               const uint32_t *__restrict__ bbase, const float *__restrict__ X,
                               const int32_t *__restrict__ l_xidx, const int64_t *__restrict__ x_off,
@@ -132,12 +147,7 @@ __global__ void k_sample_keys(int d, SampleRule rule, int n_int, int32_t B, int6
     if (gid >= S) return;
     const int64_t j = gid / n_int;
     const int q = (int)(gid % n_int);
-    int lo_b = 0, hi_b = B;
-    while (hi_b - lo_b > 1) {
-        const int mid = (lo_b + hi_b) >> 1;
-        if (s_off[mid] <= j) lo_b = mid;
-        else hi_b = mid;
-    }
+    const int lo_b = B == 1 ? 0 : (int)scloud[j];
     const GridParam g = gp[lo_b];
     float w[4];
     own_weights(rule, d, q, j - s_off[lo_b], w);
@@ -1049,6 +1059,7 @@ size_t flood_workspace(const flood_problem *pb, float alpha, FloodSizes *sz) {
     bytes += sizeof(uint32_t) * kCursorStride * (kQueues + 1) + 256;  // queue count and cursors
     bytes += 4 * (sizeof(int64_t) * (pb->B + 1) + 256); // tile offsets
     bytes += sizeof(uint32_t) * (smax / 16 + pb->B + 1) + 256;  // the cloud of every tile
+    bytes += sizeof(uint32_t) * (nmax + 1) + 256;                // the cloud of every simplex
     bytes += 1024;
     if (sz) {
         for (int d = 0; d < 4; ++d) sz->n[d] = n[d];
@@ -1111,6 +1122,7 @@ hipError_t flood_run(const flood_problem *pb, const flood_tuning &tu, const floo
     int64_t *tile_off[4];
     for (int d = 0; d < 4; ++d) tile_off[d] = c.take<int64_t>(pb->B + 1);
     uint32_t *tcloud = c.take<uint32_t>(smax / 16 + pb->B + 1);  // tiles have at least 16 samples
+    uint32_t *scloud = c.take<uint32_t>(nmax + 1);                // the cloud of every simplex
     if (!c.ok()) return hipErrorOutOfMemory;
 
     hipError_t e = hipSuccess;
@@ -1155,8 +1167,11 @@ hipError_t flood_run(const flood_problem *pb, const flood_tuning &tu, const floo
             hipLaunchKernelGGL(k_bucket_base, dim3(1), dim3(1024), 0, s, soff_d, pb->B, nint, mbits, bbase);
             e = fill_u32(bcount, 0u, bk + 1, s);
             if (e != hipSuccess) return e;
+            if (pb->B > 1)
+                hipLaunchKernelGGL(k_simplex_cloud, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, soff_d, pb->B, n,
+                                   scloud);
             hipLaunchKernelGGL(k_sample_keys, dim3((unsigned)((S + 255) / 256)), dim3(256), 0, s, d, rule, (int)nint,
-                               pb->B, S, pb->Lxyz, simp, soff_d, g.gp, mbits, bbase, pb->X, pb->l_xidx,
+                               pb->B, S, pb->Lxyz, simp, soff_d, scloud, g.gp, mbits, bbase, pb->X, pb->l_xidx,
                                pb->x_off_d, pb->landmarks_in_x, skey, srank, bcount, spos);
             e = exclusive_scan_u32(bcount, bk + 1, bscan, s);  // bucket starts
             if (e != hipSuccess) return e;
