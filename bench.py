@@ -720,7 +720,7 @@ def main():
     ap.add_argument("--diff-clouds", type=int, default=64, help="0 skips the differentiable block")
     ap.add_argument("--sweep", choices=["x", "l", "table", "all"], default=None)
     ap.add_argument("--sweep-k", type=int, default=29, help="segments per edge in the sweeps (30 points per edge)")
-    ap.add_argument("--sweep-out", type=str, default="gpurun_out/sweep.json")
+    ap.add_argument("--sweep-out", type=str, default="sweep.json")
     ap.add_argument("--write-traffic", type=str, default=None, metavar="PMC_DIR",
                     help="write profiles/traffic.json from rocprofv3 FETCH_SIZE/WRITE_SIZE runs under PMC_DIR "
                          "(pmc_fetch, pmc_write, pmc_copy_fetch, pmc_copy_write) taken at --tuning; no GPU")
