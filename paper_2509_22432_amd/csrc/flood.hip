@@ -30,7 +30,7 @@ namespace flood {
 static constexpr int kWaveBlock = 256;
 static constexpr int kTileLanesDefault[4] = {64, 64, 64, 64};  // samples per tile of the tile search, by dimension
 static constexpr uint32_t kFineMin = 8;  // shortest cell run the tile search tests against every sample
-static constexpr int kU = 4;  // points per lane per step in the per-sample search
+static constexpr int kU = 2;  // points per lane per step in the per-sample search
 static constexpr int kStage = 128;  // points staged in LDS per pass of the tile search
 
 // an open sample handed from phase A to phase B: its position and distance
