@@ -298,7 +298,7 @@ flood_status flood_filtration(const flood_problem *pb, const flood_tuning *tune,
  * until the process ends; the call itself allocates nothing.  Arguments,
  * results and errors are those of flood_filtration; FLOOD_ENOMEM (before any
  * launch) when flood_filtration_workspace_size(pb, tune) exceeds the array --
- * about 700k points at L = N/100 and k = 6.  Every call on a device uses that
+ * about 580k points at L = N/100 and k = 6.  Every call on a device uses that
  * device's one array and leaves its contents behind (each call initialises
  * what it reads), so calls that overlap on one device -- on different
  * streams or threads -- race and must be serialised by the caller.

@@ -669,11 +669,16 @@ extern "C" flood_status flood_complex_export(const flood_complex *cx, int32_t *e
         flood_host::set_error("flood_complex_export: NULL complex");
         return FLOOD_EINVAL;
     }
-    if (edges) std::memcpy(edges, cx->E.data(), cx->E.size() * sizeof(cx->E[0]));
-    if (tris) std::memcpy(tris, cx->F.data(), cx->F.size() * sizeof(cx->F[0]));
-    if (tets) std::memcpy(tets, cx->T.data(), cx->T.size() * sizeof(cx->T[0]));
-    if (tri_edges) std::memcpy(tri_edges, cx->tri_edges.data(), cx->tri_edges.size() * sizeof(cx->tri_edges[0]));
-    if (tet_tris) std::memcpy(tet_tris, cx->tet_tris.data(), cx->tet_tris.size() * sizeof(cx->tet_tris[0]));
+    // (an empty array, such as the tetrahedra of a planar complex, copies
+    // nothing: memcpy is not called with its possibly null data pointer)
+    auto put = [](int32_t *dst, const auto &v) {
+        if (dst && !v.empty()) std::memcpy(dst, v.data(), v.size() * sizeof(v[0]));
+    };
+    put(edges, cx->E);
+    put(tris, cx->F);
+    put(tets, cx->T);
+    put(tri_edges, cx->tri_edges);
+    put(tet_tris, cx->tet_tris);
     return FLOOD_OK;
 }
 
