@@ -7,8 +7,10 @@
 // of Sec. 4.1, and exactly the max over the full grid because P_tau is a
 // subset of P_sigma.
 //
-// Search, phase A (one wavefront per tile of 64*T samples that are
-// consecutive in Morton order, so a tile is spatially compact):
+// Search, phase A (one wavefront per tile of 64*T samples, or of 16 or 32
+// samples held by 4 or 2 lanes each, consecutive in Morton order, so a tile
+// is spatially compact; the sample sort computes every sample's point and
+// bound once):
 //  * each sample starts from the bound d(p,X)^2 <= min_i |p - v_i|^2, valid
 //    when the landmarks are points of X (proof of Lemma 7);
 //  * the wave scans grid cells in growing boxes around its samples, one
@@ -22,6 +24,10 @@
 //    below the distance to the unscanned region (its minimum is exact);
 //  * completed samples above the seed publish (value, rank) with a 64-bit
 //    atomic max per simplex, which other tiles read to raise M.
+// Phase B takes the samples a tile left open, one wavefront each, in rings
+// of grid rows around the sample; it keeps the nearest point's row, which
+// becomes x* when the sample wins.  The remaining winners get x* from a
+// search with the known value as radius.
 // Every skip is conservative, so the result equals the unpruned max-min.
 #include "sample.hpp"
 
