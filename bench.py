@@ -380,6 +380,10 @@ def main_block(args, torch, P, synth):
         "simplices_per_s": nsimp / (ms * 1e-3),
         "evals_per_step": ev,
         "evals_counted_in": "a separate instrumented run (median of 3); the timed steps run without counters",
+        "value_basis": ("executed sample-point distance evaluations per second of the whole step; the autotuner "
+                        "picks the tuning by wall time, and a tuning that culls more (smaller tiles) executes "
+                        "fewer evaluations, so this rate can fall while the step gets faster: simplices_per_s "
+                        "and ms_per_step compare like with like"),
         "unique_samples_per_dim": n_unique,
         "brute_force_equivalent_evals": int(sum(n_unique)) * len(X),
         "search_stats_per_dim": {"per_sample_search_ring_steps": [int(v) for v in st[:4, 0]],
