@@ -504,13 +504,52 @@ __device__ __forceinline__ float fps_box_far_d2(float lx, float ly, float lz, co
     return __fadd_rn(__fadd_rn(__fmul_rn(dx, dx), __fmul_rn(dy, dy)), __fmul_rn(dz, dz));
 }
 
+// wave reductions that end in lane 63: the four in-row DPP steps leave every
+// lane of a row holding its row's reduction, then the broadcasts of lane 15
+// (into rows 1 and 3) and of lane 31 (into rows 2 and 3) combine the rows, so
+// lane 63 holds the reduction of all 64 lanes and one scalar read fetches it
+// (lanes of the rows a broadcast leaves out are never read).  All 64 lanes
+// active.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ uint32_t dpp_max_rows(uint32_t v) {
+    return max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, ROWS, 0xf, true));
+}
+template <int CTRL, int ROWS>
+__device__ __forceinline__ uint32_t dpp_min_rows(uint32_t v) {
+    return min(v, (uint32_t)__builtin_amdgcn_update_dpp(-1, (int)v, CTRL, ROWS, 0xf, true));
+}
+__device__ __forceinline__ uint32_t wave_max_u32_l63(uint32_t v) {
+    v = dpp_max_u32<0x140>(dpp_max_u32<0x141>(dpp_max_u32<0x4e>(dpp_max_u32<0xb1>(v))));
+    v = dpp_max_rows<0x143, 0xc>(dpp_max_rows<0x142, 0xa>(v));
+    return rd_lane(v, 63);
+}
+__device__ __forceinline__ uint32_t wave_min_u32_l63(uint32_t v) {
+    v = dpp_min_u32<0x140>(dpp_min_u32<0x141>(dpp_min_u32<0x4e>(dpp_min_u32<0xb1>(v))));
+    v = dpp_min_rows<0x143, 0xc>(dpp_min_rows<0x142, 0xa>(v));
+    return rd_lane(v, 63);
+}
+// the writelane intrinsic (v_writelane_b32): old with lane l replaced by the
+// uniform value v
+__device__ int32_t amdgcn_writelane(int32_t v, int32_t l, int32_t old) __asm("llvm.amdgcn.writelane.i32");
+// the largest of non-negative floats (ordered as their bits)
+__device__ __forceinline__ float wave_max_nonneg(float v) { return __uint_as_float(wave_max_u32_l63(__float_as_uint(v))); }
+// the lane holding the wave's largest key (mb << 32) | ~id: the largest mb,
+// and among equal mb the lowest id; mmax gets that mb
+__device__ __forceinline__ int wave_argmax_key63(uint32_t mb, uint32_t id, uint32_t &mmax) {
+    mmax = wave_max_u32_l63(mb);
+    const uint64_t tied = __ballot(mb == mmax);
+    int src = __ffsll((unsigned long long)tied) - 1;
+    if (__popcll(tied) != 1) {
+        const uint32_t umin = wave_min_u32_l63(mb == mmax ? id : 0xffffffffu);
+        src = __ffsll((unsigned long long)__ballot(mb == mmax && id == umin)) - 1;
+    }
+    return src;
+}
+
 // an exchanged word: 32-bit payload, 32-bit exchange number
 __device__ __forceinline__ uint64_t xw(uint32_t payload, uint32_t id) { return ((uint64_t)payload << 32) | id; }
 __device__ __forceinline__ uint32_t xw_val(uint64_t w) { return (uint32_t)(w >> 32); }
 __device__ __forceinline__ bool xw_ok(uint64_t w, uint32_t id) { return (uint32_t)w == id; }
-
-// the largest key a point of running minimum m can carry (any index)
-__device__ __forceinline__ uint64_t key_bound(float m) { return ((uint64_t)__float_as_uint(m) << 32) | 0xffffffffull; }
 
 // keep the three largest (key, slot) pairs
 __device__ __forceinline__ void top3_insert(uint64_t (&k)[3], int (&s)[3], uint64_t v, int sv) {
@@ -733,14 +772,14 @@ __global__ __launch_bounds__(256) void k_fps_coop(
                     }
                 }
                 uint32_t kmb;
-                const int src = wave_argmax_key((uint32_t)(kb >> 32), 0xffffffffu - (uint32_t)kb, kmb);
+                const int src = wave_argmax_key63((uint32_t)(kb >> 32), 0xffffffffu - (uint32_t)kb, kmb);
                 const uint64_t km = ((uint64_t)kmb << 32) | rd_lane((uint32_t)kb, src);
                 bx = __uint_as_float(rd_lane(__float_as_uint(bx), src));
                 by = __uint_as_float(rd_lane(__float_as_uint(by), src));
                 bz = __uint_as_float(rd_lane(__float_as_uint(bz), src));
                 // second minimum of the chunk: every lane's best except the
                 // chunk's best point, and every lane's second
-                const float sec = wave_max_f32_dpp(lane == src ? m2 : fmaxf(mb, m2));
+                const float sec = wave_max_nonneg(lane == src ? m2 : fmaxf(mb, m2));
                 if (init) {
 #pragma unroll
                     for (int o = 32; o > 0; o >>= 1) {
@@ -792,7 +831,7 @@ __global__ __launch_bounds__(256) void k_fps_coop(
 #pragma unroll
             for (int r = 0; r < 3; ++r) {
                 uint32_t hb;
-                const int src = wave_argmax_key((uint32_t)(tk[0] >> 32), 0xffffffffu - (uint32_t)tk[0], hb);
+                const int src = wave_argmax_key63((uint32_t)(tk[0] >> 32), 0xffffffffu - (uint32_t)tk[0], hb);
                 const uint64_t kw = ((uint64_t)hb << 32) | rd_lane((uint32_t)tk[0], src);
                 const int sw = (int)rd_lane((uint32_t)ts[0], src);
                 if (lane == 0) {
@@ -899,7 +938,7 @@ __global__ __launch_bounds__(256) void k_fps_coop(
                     kb = k[c] > kb ? k[c] : kb;
                 }
                 uint32_t hbest;
-                const int ksrc = wave_argmax_key((uint32_t)(kb >> 32), 0xffffffffu - (uint32_t)kb, hbest);
+                const int ksrc = wave_argmax_key63((uint32_t)(kb >> 32), 0xffffffffu - (uint32_t)kb, hbest);
                 const uint64_t ktop = ((uint64_t)hbest << 32) | rd_lane((uint32_t)kb, ksrc);
                 uint32_t th = 0;
                 for (int bit = 30; bit >= 0; --bit) {  // minima are non-negative floats
@@ -928,7 +967,7 @@ __global__ __launch_bounds__(256) void k_fps_coop(
                     base += __popcll(m);
                 }
                 if (lane >= base && lane < kT) s_cand[wid * kT + lane].key = 0;
-                const float bmax = wave_max_f32_dpp(w < W ? bw : 0.f);
+                const float bmax = wave_max_nonneg(w < W ? bw : 0.f);
                 if (lane == 0) s_bnd[wid] = fmaxf(bmax, __uint_as_float(th));
             }
             __syncthreads();
@@ -936,64 +975,75 @@ __global__ __launch_bounds__(256) void k_fps_coop(
             int j = 0;
             if (all_in && wid == 0) {
                 // one wave replays the greedy rule on the NW * kT kept
-                // candidates, kR per lane
+                // candidates, kR per lane.  Minima and bounds are held as the
+                // bits of non-negative floats (ordered as unsigned integers);
+                // an empty slot holds minimum 0, bound 0 and index ~0, so it
+                // never wins against a candidate and never lowers a bound
                 constexpr int kR = NW * kT / 64;
-                bool alive[kR];
-                float m[kR], b[kR], x[kR], y[kR], z[kR], bb[kR][6];
-                uint32_t lid[kR];
+                uint32_t m[kR], b[kR], lid[kR];
+                float x[kR], y[kR], z[kR], bb[kR][6];
 #pragma unroll
                 for (int r = 0; r < kR; ++r) {
                     const Cand &o = s_cand[lane + 64 * r];
-                    alive[r] = o.key != 0;
-                    m[r] = __uint_as_float((uint32_t)(o.key >> 32));
-                    b[r] = o.cb;
-                    lid[r] = 0xffffffffu - (uint32_t)o.key;
+                    const bool alive = o.key != 0;
+                    m[r] = alive ? (uint32_t)(o.key >> 32) : 0u;
+                    b[r] = alive ? __float_as_uint(o.cb) : 0u;
+                    lid[r] = alive ? 0xffffffffu - (uint32_t)o.key : 0xffffffffu;
                     x[r] = o.x;
                     y[r] = o.y;
                     z[r] = o.z;
 #pragma unroll
                     for (int f = 0; f < 6; ++f) bb[r][f] = o.bb[f];
                 }
-                const float b0 = fmaxf(fmaxf(s_bnd[0], s_bnd[1]), fmaxf(s_bnd[2], s_bnd[3]));
+                const uint32_t b0 = __builtin_amdgcn_readfirstlane(
+                    __float_as_uint(fmaxf(fmaxf(s_bnd[0], s_bnd[1]), fmaxf(s_bnd[2], s_bnd[3]))));
+                // lane p keeps pick p until the replay ends
+                uint32_t pk_i = 0, pk_m = 0, pk_x = 0, pk_y = 0, pk_z = 0;
                 for (int p = 0; p < jcap; ++p) {
                     // this lane's best candidate (largest minimum, then lowest index)
-                    uint32_t mb = alive[0] ? __float_as_uint(m[0]) : 0u, ib = alive[0] ? lid[0] : 0xffffffffu;
-                    float hb = alive[0] ? b[0] : 0.f, bx = x[0], by = y[0], bz = z[0];
+                    uint32_t mb = m[0], ib = lid[0], hb = b[0];
+                    float bx = x[0], by = y[0], bz = z[0];
 #pragma unroll
                     for (int r = 1; r < kR; ++r) {
-                        if (!alive[r]) continue;
-                        const uint32_t mr = __float_as_uint(m[r]);
-                        if (mr > mb || (mr == mb && lid[r] < ib)) {
-                            mb = mr;
+                        if (m[r] > mb || (m[r] == mb && lid[r] < ib)) {
+                            mb = m[r];
                             ib = lid[r];
                             bx = x[r];
                             by = y[r];
                             bz = z[r];
                         }
-                        hb = fmaxf(hb, b[r]);
+                        hb = max(hb, b[r]);
                     }
                     uint32_t mmax;
-                    const int src = wave_argmax_key(mb, ib, mmax);
-                    const uint64_t best = ((uint64_t)mmax << 32) | (0xffffffffu - rd_lane(ib, src));
-                    if (p > 0 && (!(best > key_bound(b0)) || __ballot(!(best > key_bound(hb))))) break;
+                    const int src = wave_argmax_key63(mb, ib, mmax);
+                    // a key (mmax << 32 | ~index) exceeds every key whose
+                    // minimum is at most a bound exactly when mmax exceeds the
+                    // bound's bits
+                    if (p > 0 && (!(mmax > b0) || __ballot(!(mmax > hb)))) break;
+                    const uint32_t pid = rd_lane(ib, src);
                     const float px = __uint_as_float(rd_lane(__float_as_uint(bx), src));
                     const float py = __uint_as_float(rd_lane(__float_as_uint(by), src));
                     const float pz = __uint_as_float(rd_lane(__float_as_uint(bz), src));
-                    if (lane == 0) {
-                        s_pick[p][0] = 0xffffffffu - (uint32_t)best;
-                        s_pick[p][1] = (uint32_t)(best >> 32);
-                        s_pick[p][2] = __float_as_uint(px);
-                        s_pick[p][3] = __float_as_uint(py);
-                        s_pick[p][4] = __float_as_uint(pz);
-                    }
+                    pk_i = (uint32_t)amdgcn_writelane((int)pid, p, (int)pk_i);
+                    pk_m = (uint32_t)amdgcn_writelane((int)mmax, p, (int)pk_m);
+                    pk_x = (uint32_t)amdgcn_writelane((int)__float_as_uint(px), p, (int)pk_x);
+                    pk_y = (uint32_t)amdgcn_writelane((int)__float_as_uint(py), p, (int)pk_y);
+                    pk_z = (uint32_t)amdgcn_writelane((int)__float_as_uint(pz), p, (int)pk_z);
                     ++j;
                     // the candidates and their chunks' bounds after this pick
+                    // (both distances are non-negative floats)
 #pragma unroll
                     for (int r = 0; r < kR; ++r) {
-                        if (!alive[r]) continue;
-                        m[r] = fminf(m[r], fps_d2(x[r], y[r], z[r], px, py, pz));
-                        b[r] = fminf(b[r], fps_box_far_d2(px, py, pz, bb[r]));
+                        m[r] = min(m[r], __float_as_uint(fps_d2(x[r], y[r], z[r], px, py, pz)));
+                        b[r] = min(b[r], __float_as_uint(fps_box_far_d2(px, py, pz, bb[r])));
                     }
+                }
+                if (lane < j) {
+                    s_pick[lane][0] = pk_i;
+                    s_pick[lane][1] = pk_m;
+                    s_pick[lane][2] = pk_x;
+                    s_pick[lane][3] = pk_y;
+                    s_pick[lane][4] = pk_z;
                 }
             }
             __syncthreads();
