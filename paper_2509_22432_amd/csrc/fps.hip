@@ -641,6 +641,11 @@ __global__ __launch_bounds__(256) void k_fps_coop(
     for (uint32_t e = 0;; ++e) {
         const bool init = e == 0;
         const int np = s_np;
+        // landmark t of this exchange in lane t of every wave (for reads by
+        // a uniform lane index: no LDS round trip per landmark)
+        const float pk_lx = lane < np ? s_pk[lane][0] : 0.f;
+        const float pk_ly = lane < np ? s_pk[lane][1] : 0.f;
+        const float pk_lz = lane < np ? s_pk[lane][2] : 0.f;
         // 1. the chunks some landmark can lower (all of them at first)
         int naff;
         if (init) {
@@ -738,7 +743,9 @@ __global__ __launch_bounds__(256) void k_fps_coop(
                 for (int u = 0; u < M; ++u) d2v[u] = mm[c * M + u];
                 for (LMask mk = msk[c]; mk; mk &= mk - 1u) {
                     const int t = __builtin_ctzll((unsigned long long)mk);
-                    const float lx = s_pk[t][0], ly = s_pk[t][1], lz = s_pk[t][2];
+                    const float lx = __uint_as_float(rd_lane(__float_as_uint(pk_lx), t));
+                    const float ly = __uint_as_float(rd_lane(__float_as_uint(pk_ly), t));
+                    const float lz = __uint_as_float(rd_lane(__float_as_uint(pk_lz), t));
 #pragma unroll
                     for (int u = 0; u < M; ++u) {
                         const int i = c * M + u;
