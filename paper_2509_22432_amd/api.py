@@ -54,9 +54,22 @@ def fps_batched(X: torch.Tensor, x_off, n_lm, start=None, check_indices: bool = 
     n_lm_h = np.ascontiguousarray(np.asarray(n_lm, dtype=np.int32))
     if len(n_lm_h) != B:
         raise ValueError("n_lm must have one entry per cloud")
-    x_off_d = _dev(x_off_h, torch.int64, dev)
-    n_lm_d = _dev(n_lm_h, torch.int32, dev)
-    start_d = _dev(np.asarray(start, np.int64), torch.int64, dev) if start is not None else None
+    # the per-cloud arrays go up in one copy: x_off and start (int64), then
+    # n_lm (int32), each at an 8-byte aligned offset of one byte buffer
+    start_h = np.ascontiguousarray(np.asarray(start, np.int64)) if start is not None else np.zeros(0, np.int64)
+    if start is not None and len(start_h) != B:
+        raise ValueError("start must have one entry per cloud")
+    o_start = 8 * (B + 1)
+    o_nlm = o_start + 8 * len(start_h)
+    packed = np.zeros(o_nlm + 4 * B, np.uint8)
+    packed[:o_start] = x_off_h.view(np.uint8)
+    packed[o_start:o_nlm] = start_h.view(np.uint8)
+    packed[o_nlm:] = n_lm_h.view(np.uint8)
+    packed_d = torch.from_numpy(packed).to(dev)
+    base = packed_d.data_ptr()
+    x_off_d = ctypes.c_void_p(base)
+    start_d = ctypes.c_void_p(base + o_start) if start is not None else ctypes.c_void_p(0)
+    n_lm_d = ctypes.c_void_p(base + o_nlm)
     tot = int(n_lm_h.sum())
     idx = torch.empty(tot, dtype=torch.int32, device=dev)
     radius = torch.empty(tot, dtype=torch.float32, device=dev)
@@ -64,7 +77,7 @@ def fps_batched(X: torch.Tensor, x_off, n_lm, start=None, check_indices: bool = 
     n_lm_p = n_lm_h.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
     ws_n = L.flood_fps_workspace_size(B, x_off_p, n_lm_p)
     ws = torch.empty(max(ws_n, 1), dtype=torch.uint8, device=dev)
-    check(L.flood_fps(_ptr(X), B, x_off_p, _ptr(x_off_d), n_lm_p, _ptr(n_lm_d), _ptr(start_d), _ptr(idx),
+    check(L.flood_fps(_ptr(X), B, x_off_p, x_off_d, n_lm_p, n_lm_d, start_d, _ptr(idx),
                       _ptr(radius), _ptr(ws), ws_n, _stream()))
     if check_indices:
         check_landmarks(idx)
