@@ -580,19 +580,23 @@ __device__ __forceinline__ uint64_t uniform_mask(uint64_t m) {
 }
 
 template <int LM>
-__global__ __launch_bounds__(256) void k_fps_coop(
+__global__ __launch_bounds__(512) void k_fps_coop(
     CoopArgs a, const float *__restrict__ X, const GridParam *__restrict__ gp, const float4 *__restrict__ xs,
     float *__restrict__ mind, uint64_t *__restrict__ rec, uint64_t *__restrict__ dec, uint32_t *__restrict__ ctl,
     const int64_t *__restrict__ start, int32_t *__restrict__ idx_out, float *__restrict__ radius) {
-    constexpr int NT = 256;
+    // eight waves (two per SIMD at about 200 registers): the chunk tests,
+    // updates and top three spread over all of them; the records are
+    // collected by the first NWC, one workgroup per lane
+    constexpr int NT = 512;
     constexpr int NW = NT / 64;
+    constexpr int NWC = kMaxWG / 64;
     constexpr int M = 1 << LM;          // points per lane per chunk
     constexpr int U = 8 >> LM;          // chunks per wave step
     constexpr int SCOPE = __HIP_MEMORY_SCOPE_AGENT;
     constexpr int DH = (1 + 5 * kJ + 63) / 64;  // decision words a lane reads
     static_assert(1 + 12 * kK <= kRec && 1 + 12 * kK <= 64 && 1 + 5 * kJ <= kDec && kDec <= 64 * DH && kK <= 2,
                   "exchange layout");
-    static_assert(NW * kT % 64 == 0 && kT <= 64, "whole kept candidates per lane of the replaying wave");
+    static_assert(NWC * kT % 64 == 0 && kT <= 64 && NWC <= NW, "whole kept candidates per lane of the replaying wave");
     static_assert(kJ <= 8 * (int)sizeof(LMask), "landmark masks");
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ float s_pk[kJ][3];       // landmarks to apply
@@ -604,7 +608,7 @@ __global__ __launch_bounds__(256) void k_fps_coop(
         uint64_t key;                    // 0: no candidate
         float cb, x, y, z, bb[6];
     };
-    __shared__ Cand s_cand[NW * kT];     // the leader's kept candidates
+    __shared__ Cand s_cand[NWC * kT];    // the leader's kept candidates
     __shared__ float s_bnd[NW];          // bound of the candidates each wave did not keep
     __shared__ uint32_t s_pick[kJ][5];   // the leader's picks
     __shared__ int s_wok[NW];
@@ -887,106 +891,109 @@ __global__ __launch_bounds__(256) void k_fps_coop(
         uint64_t *my_dec = dec + (size_t)(e & 1) * kDec;
         const int jcap = min(kJ, a.nl + 1 - t_done);
         if (wg == 0) {
-            // 5. the leader: every lane collects one workgroup's record, then
-            //    the four waves replay the greedy rule together
-            const int w = wid * 64 + lane;
-            float cm[kK], cxp[kK], cyp[kK], czp[kK], cb[kK], cbb[kK][6], bw = 0.f;
-            uint32_t cid[kK];
-            bool valid[kK];
-            bool done = false;
-            for (int spin = 0; spin < kSpinLimit && !done; ++spin) {
-                bool ok = true;
+            // 5. the leader: the first NWC waves collect the records, one
+            //    workgroup's per lane, and keep their best candidates; then
+            //    one wave replays the greedy rule on the kept ones
+            if (wid < NWC) {
+                const int w = wid * 64 + lane;
+                float cm[kK], cxp[kK], cyp[kK], czp[kK], cb[kK], cbb[kK][6], bw = 0.f;
+                uint32_t cid[kK];
+                bool valid[kK];
+                bool done = false;
+                for (int spin = 0; spin < kSpinLimit && !done; ++spin) {
+                    bool ok = true;
 #pragma unroll
-                for (int c = 0; c < kK; ++c) valid[c] = false;
-                if (w < W) {
-                    const uint64_t *rw = rec + (size_t)(e & 1) * kRec * kMaxWG + w;
-                    const uint64_t w0 = __hip_atomic_load(&rw[0], __ATOMIC_RELAXED, SCOPE);
-                    ok &= xw_ok(w0, id);
-                    bw = __uint_as_float(xw_val(w0));
+                    for (int c = 0; c < kK; ++c) valid[c] = false;
+                    if (w < W) {
+                        const uint64_t *rw = rec + (size_t)(e & 1) * kRec * kMaxWG + w;
+                        const uint64_t w0 = __hip_atomic_load(&rw[0], __ATOMIC_RELAXED, SCOPE);
+                        ok &= xw_ok(w0, id);
+                        bw = __uint_as_float(xw_val(w0));
+#pragma unroll
+                        for (int c = 0; c < kK; ++c) {
+                            uint32_t v[12];
+#pragma unroll
+                            for (int f = 0; f < 12; ++f) {
+                                const uint64_t x = __hip_atomic_load(&rw[(size_t)(1 + 12 * c + f) * kMaxWG], __ATOMIC_RELAXED, SCOPE);
+                                ok &= xw_ok(x, id);
+                                v[f] = xw_val(x);
+                            }
+                            valid[c] = v[1] != 0xffffffffu;
+                            cm[c] = __uint_as_float(v[0]);
+                            cid[c] = v[1];
+                            cxp[c] = __uint_as_float(v[2]);
+                            cyp[c] = __uint_as_float(v[3]);
+                            czp[c] = __uint_as_float(v[4]);
+                            cb[c] = __uint_as_float(v[5]);
+#pragma unroll
+                            for (int f = 0; f < 6; ++f) cbb[c][f] = __uint_as_float(v[6 + f]);
+                        }
+                    }
+                    done = __all(ok);
+                    if (!done) __builtin_amdgcn_s_sleep(1);
+                }
+                if (lane == 0) s_wok[wid] = done ? 1 : 0;
+                {
+                    // every wave keeps its best key and the candidates whose
+                    // minimum exceeds theta, the kT-th largest minimum it holds
+                    // (found bit by bit, so at most kT - 1 lie above it); the
+                    // points of every other chunk it holds have running minima of
+                    // at most max(theta, the next-chunk bounds), since a chunk's
+                    // second minimum never exceeds its best
+                    uint64_t k[kK];
+                    uint32_t mk[kK];
+                    uint64_t kb = 0;
 #pragma unroll
                     for (int c = 0; c < kK; ++c) {
-                        uint32_t v[12];
+                        const bool vc = w < W && valid[c];
+                        mk[c] = vc ? __float_as_uint(cm[c]) : 0u;
+                        k[c] = vc ? ((uint64_t)mk[c] << 32) | (uint64_t)(0xffffffffu - cid[c]) : 0;
+                        kb = k[c] > kb ? k[c] : kb;
+                    }
+                    uint32_t hbest;
+                    const int ksrc = wave_argmax_key63((uint32_t)(kb >> 32), 0xffffffffu - (uint32_t)kb, hbest);
+                    const uint64_t ktop = ((uint64_t)hbest << 32) | rd_lane((uint32_t)kb, ksrc);
+                    uint32_t th = 0;
+                    for (int bit = 30; bit >= 0; --bit) {  // minima are non-negative floats
+                        const uint32_t t = th | (1u << bit);
+                        int cnt = 0;
 #pragma unroll
-                        for (int f = 0; f < 12; ++f) {
-                            const uint64_t x = __hip_atomic_load(&rw[(size_t)(1 + 12 * c + f) * kMaxWG], __ATOMIC_RELAXED, SCOPE);
-                            ok &= xw_ok(x, id);
-                            v[f] = xw_val(x);
+                        for (int c = 0; c < kK; ++c) cnt += __popcll(__ballot(mk[c] >= t));
+                        if (cnt >= kT) th = t;
+                    }
+                    const uint64_t below = (1ull << lane) - 1ull;
+                    int base = 0;
+#pragma unroll
+                    for (int c = 0; c < kK; ++c) {
+                        const bool in = k[c] != 0 && (mk[c] > th || k[c] == ktop);
+                        const uint64_t m = __ballot(in);
+                        if (in) {
+                            Cand &o = s_cand[wid * kT + base + __popcll(m & below)];
+                            o.key = k[c];
+                            o.cb = cb[c];
+                            o.x = cxp[c];
+                            o.y = cyp[c];
+                            o.z = czp[c];
+#pragma unroll
+                            for (int f = 0; f < 6; ++f) o.bb[f] = cbb[c][f];
                         }
-                        valid[c] = v[1] != 0xffffffffu;
-                        cm[c] = __uint_as_float(v[0]);
-                        cid[c] = v[1];
-                        cxp[c] = __uint_as_float(v[2]);
-                        cyp[c] = __uint_as_float(v[3]);
-                        czp[c] = __uint_as_float(v[4]);
-                        cb[c] = __uint_as_float(v[5]);
-#pragma unroll
-                        for (int f = 0; f < 6; ++f) cbb[c][f] = __uint_as_float(v[6 + f]);
+                        base += __popcll(m);
                     }
+                    if (lane >= base && lane < kT) s_cand[wid * kT + lane].key = 0;
+                    const float bmax = wave_max_nonneg(w < W ? bw : 0.f);
+                    if (lane == 0) s_bnd[wid] = fmaxf(bmax, __uint_as_float(th));
                 }
-                done = __all(ok);
-                if (!done) __builtin_amdgcn_s_sleep(1);
-            }
-            if (lane == 0) s_wok[wid] = done ? 1 : 0;
-            {
-                // every wave keeps its best key and the candidates whose
-                // minimum exceeds theta, the kT-th largest minimum it holds
-                // (found bit by bit, so at most kT - 1 lie above it); the
-                // points of every other chunk it holds have running minima of
-                // at most max(theta, the next-chunk bounds), since a chunk's
-                // second minimum never exceeds its best
-                uint64_t k[kK];
-                uint32_t mk[kK];
-                uint64_t kb = 0;
-#pragma unroll
-                for (int c = 0; c < kK; ++c) {
-                    const bool vc = w < W && valid[c];
-                    mk[c] = vc ? __float_as_uint(cm[c]) : 0u;
-                    k[c] = vc ? ((uint64_t)mk[c] << 32) | (uint64_t)(0xffffffffu - cid[c]) : 0;
-                    kb = k[c] > kb ? k[c] : kb;
-                }
-                uint32_t hbest;
-                const int ksrc = wave_argmax_key63((uint32_t)(kb >> 32), 0xffffffffu - (uint32_t)kb, hbest);
-                const uint64_t ktop = ((uint64_t)hbest << 32) | rd_lane((uint32_t)kb, ksrc);
-                uint32_t th = 0;
-                for (int bit = 30; bit >= 0; --bit) {  // minima are non-negative floats
-                    const uint32_t t = th | (1u << bit);
-                    int cnt = 0;
-#pragma unroll
-                    for (int c = 0; c < kK; ++c) cnt += __popcll(__ballot(mk[c] >= t));
-                    if (cnt >= kT) th = t;
-                }
-                const uint64_t below = (1ull << lane) - 1ull;
-                int base = 0;
-#pragma unroll
-                for (int c = 0; c < kK; ++c) {
-                    const bool in = k[c] != 0 && (mk[c] > th || k[c] == ktop);
-                    const uint64_t m = __ballot(in);
-                    if (in) {
-                        Cand &o = s_cand[wid * kT + base + __popcll(m & below)];
-                        o.key = k[c];
-                        o.cb = cb[c];
-                        o.x = cxp[c];
-                        o.y = cyp[c];
-                        o.z = czp[c];
-#pragma unroll
-                        for (int f = 0; f < 6; ++f) o.bb[f] = cbb[c][f];
-                    }
-                    base += __popcll(m);
-                }
-                if (lane >= base && lane < kT) s_cand[wid * kT + lane].key = 0;
-                const float bmax = wave_max_nonneg(w < W ? bw : 0.f);
-                if (lane == 0) s_bnd[wid] = fmaxf(bmax, __uint_as_float(th));
             }
             __syncthreads();
             const bool all_in = s_wok[0] && s_wok[1] && s_wok[2] && s_wok[3];
             int j = 0;
             if (all_in && wid == 0) {
-                // one wave replays the greedy rule on the NW * kT kept
+                // one wave replays the greedy rule on the NWC * kT kept
                 // candidates, kR per lane.  Minima and bounds are held as the
                 // bits of non-negative floats (ordered as unsigned integers);
                 // an empty slot holds minimum 0, bound 0 and index ~0, so it
                 // never wins against a candidate and never lowers a bound
-                constexpr int kR = NW * kT / 64;
+                constexpr int kR = NWC * kT / 64;
                 uint32_t m[kR], b[kR], lid[kR];
                 float x[kR], y[kR], z[kR], bb[kR][6];
 #pragma unroll
@@ -1144,7 +1151,7 @@ static hipError_t launch_coop(const CoopArgs &a, int grid, int shmem, const floa
     if (e != hipSuccess) return e;
     CoopArgs aa = a;
     void *args[] = {&aa, (void *)&X, (void *)&gp, (void *)&xs, &mind, &rec, &dec, &ctl, (void *)&start, &idx, &radius};
-    return hipLaunchCooperativeKernel((const void *)k_fps_coop<LM>, dim3(grid), dim3(256), args, (unsigned)shmem, s);
+    return hipLaunchCooperativeKernel((const void *)k_fps_coop<LM>, dim3(grid), dim3(512), args, (unsigned)shmem, s);
 }
 
 static int device_cus() {
