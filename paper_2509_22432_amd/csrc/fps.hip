@@ -579,19 +579,24 @@ __device__ __forceinline__ uint64_t uniform_mask(uint64_t m) {
            ((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(m >> 32)) << 32);
 }
 
+// threads of a cooperative workgroup: twelve waves for chunks of 64 points
+// (three per SIMD: the kernel fits in 168 registers when the update takes
+// four chunks per wave step), eight for larger chunks (two per SIMD)
+constexpr int coop_threads(int lm) { return lm == 0 ? 768 : 512; }
+
 template <int LM>
-__global__ __launch_bounds__(512) void k_fps_coop(
+__global__ __launch_bounds__(coop_threads(LM)) void k_fps_coop(
     CoopArgs a, const float *__restrict__ X, const GridParam *__restrict__ gp, const float4 *__restrict__ xs,
     float *__restrict__ mind, uint64_t *__restrict__ rec, uint64_t *__restrict__ dec, uint32_t *__restrict__ ctl,
     const int64_t *__restrict__ start, int32_t *__restrict__ idx_out, float *__restrict__ radius) {
-    // eight waves (two per SIMD at about 200 registers): the chunk tests,
-    // updates and top three spread over all of them; the records are
-    // collected by the first NWC, one workgroup per lane
-    constexpr int NT = 512;
+    // the chunk tests, updates and top three spread over all the waves; the
+    // records are collected by the first NWC, one workgroup per lane
+    constexpr int NT = coop_threads(LM);
     constexpr int NW = NT / 64;
     constexpr int NWC = kMaxWG / 64;
     constexpr int M = 1 << LM;          // points per lane per chunk
-    constexpr int U = 8 >> LM;          // chunks per wave step
+    constexpr int U = LM == 0 ? 4 : 8 >> LM;  // chunks per wave step
+    constexpr int P = U * M;            // points per lane per wave step
     constexpr int SCOPE = __HIP_MEMORY_SCOPE_AGENT;
     constexpr int DH = (1 + 5 * kJ + 63) / 64;  // decision words a lane reads
     static_assert(1 + 12 * kK <= kRec && 1 + 12 * kK <= 64 && 1 + 5 * kJ <= kDec && kDec <= 64 * DH && kK <= 2,
@@ -706,9 +711,9 @@ __global__ __launch_bounds__(512) void k_fps_coop(
         //    running minimum of the chunk as it is): running minima, best key
         //    and point, second minimum
         for (int e0 = 0; e0 < naff; e0 += NW * U) {  // list entries e0 + c * NW + wid
-            float4 q[8];
-            float mm[8];
-            int64_t pp[8];
+            float4 q[P];
+            float mm[P];
+            int64_t pp[P];
             int sl[U];
             LMask msk[U];
 #pragma unroll
@@ -722,7 +727,7 @@ __global__ __launch_bounds__(512) void k_fps_coop(
                 }
             }
 #pragma unroll
-            for (int i = 0; i < 8; ++i) {
+            for (int i = 0; i < P; ++i) {
                 const int c = i >> LM, u = i & (M - 1);
                 pp[i] = -1;
                 if (sl[c] >= 0) {
@@ -1151,7 +1156,7 @@ static hipError_t launch_coop(const CoopArgs &a, int grid, int shmem, const floa
     if (e != hipSuccess) return e;
     CoopArgs aa = a;
     void *args[] = {&aa, (void *)&X, (void *)&gp, (void *)&xs, &mind, &rec, &dec, &ctl, (void *)&start, &idx, &radius};
-    return hipLaunchCooperativeKernel((const void *)k_fps_coop<LM>, dim3(grid), dim3(512), args, (unsigned)shmem, s);
+    return hipLaunchCooperativeKernel((const void *)k_fps_coop<LM>, dim3(grid), dim3(coop_threads(LM)), args, (unsigned)shmem, s);
 }
 
 static int device_cus() {
